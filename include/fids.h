@@ -1,0 +1,200 @@
+/*
+ * fids.h -- C ABI of the MI355X (gfx950) library for the fast implicit
+ * difference scheme (FIDS) of the 1-D time-space fractional diffusion
+ * equation with the integral fractional Laplacian:
+ *
+ *     D_t^gamma u = -kappa(x,t) (-Delta)^{alpha/2} u + f   on (-l, l) x (0, T],
+ *     u = 0 outside (-l, l),   u(x, 0) = phi(x)                        (eq. 1.1)
+ *
+ * Discretisation (Sec. 2.1): N_p = n + 1 spatial intervals, h = 2l/N_p,
+ * interior nodes x_i = -l + i h (i = 1..n, array index i-1); graded time
+ * levels t_m = T (m/M)^r; graded L1 formula with the sum-of-exponentials
+ * (SOE) history of Lemma 2.2 / eq. (2.9); IFL matrix A of eq. (3.16x).
+ * Each time level solves the matrix form (3.16gu)
+ *
+ *     (g b_m I + K_m A) u^m = g [b_m u^{m-1} - sum_j w_j F_j^{(m)}] + f^m,
+ *
+ * g = 1/Gamma(1-gamma), K_m = diag(kappa(x_i, t_m)), with a Krylov method
+ * preconditioned by Strang's circulant (eq. 4.3).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments whose names end in _d are DEVICE pointers (HIP global
+ *     memory on the device that is current when the handle is created), owned
+ *     by the caller.  kappa_d / f_d / phi_d are BORROWED: the library keeps the
+ *     pointers and reads them during fids_step / fids_solve_all /
+ *     fids_adjoint, so they must stay alive and unchanged until fids_destroy.
+ *   - All device work is enqueued on the hip_stream given at creation (NULL =
+ *     the default stream).  Calls that return device results (u_out_d, uT_d,
+ *     gradients) enqueue the writes and synchronise the stream before they
+ *     return, because they also report a status computed on the device.
+ *   - The library never calls hipMalloc: all device memory it uses lives in
+ *     the caller's workspace ws_d of at least fids_workspace_size() bytes
+ *     (256-byte aligned).  Host memory for the handle and the set-up tables is
+ *     allocated with malloc/new and released by fids_destroy.
+ *   - Status codes: FIDS_OK = 0 or one of the negative FIDS_E* values below;
+ *     no C++ exception crosses the ABI.  A handle is not thread safe; use one
+ *     handle per host thread / stream.
+ *   - Layouts: kappa_d is [M][n] with row m-1 = kappa(x_i, t_m) when
+ *     kappa_time_dependent != 0, else [n]; f_d is [M][n] with row m-1 =
+ *     f(x_i, t_m); phi_d and every u vector are [n]; u_all_d is [M+1][n]
+ *     with row m = u^m.  All are dense row-major FP64.
+ */
+#ifndef FIDS_H
+#define FIDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define FIDS_OK        0
+#define FIDS_EINVAL   -1  /* bad parameter, null pointer, workspace too small     */
+#define FIDS_EDEVICE  -2  /* a HIP runtime call failed                             */
+#define FIDS_ENOCONV  -3  /* Krylov maxit reached or breakdown; the step is not    */
+                          /* advanced and the step info holds iters and relres     */
+#define FIDS_ENUMERIC -4  /* NaN/Inf met on the device                             */
+#define FIDS_ESTATE   -5  /* step after M, adjoint without stored forward states  */
+
+/* ------------------------------------------------------------ knobs */
+#define FIDS_BICGSTAB 0   /* right-preconditioned BiCGSTAB (the paper's solver, Sec. 5) */
+#define FIDS_FGMRES   1   /* flexible GMRES(restart), right preconditioning          */
+#define FIDS_FP64     0   /* every FFT, vector and reduction in FP64                 */
+#define FIDS_MIXED    1   /* preconditioner FFTs in FP32, everything else FP64       */
+#define FIDS_STRANG   0   /* Strang circulant preconditioner, eq. (4.3)              */
+#define FIDS_NONE     1   /* no preconditioner (identity)                            */
+
+/* Problem statement (1.1) plus discretisation and solver knobs.
+ * Fill with fids_params_default() first, then set what differs. */
+typedef struct fids_params {
+    double  alpha;        /* IFL order, (0, 2)                                     */
+    double  gamma;        /* Caputo order, (0, 1)                                  */
+    double  l;            /* half-width of the domain (-l, l), > 0                 */
+    double  T;            /* final time, > 0                                       */
+    int64_t n;            /* interior unknowns per level (paper: N - 1), >= 1      */
+    int64_t M;            /* number of graded time levels, >= 1                    */
+    double  r;            /* grading exponent t_m = T (m/M)^r, >= 1                */
+    double  mu;           /* splitting parameter of (2.11), (alpha, 2]; 0 selects  */
+                          /* 1 + alpha/2; kappa_mu = 2 when mu == 2 else 1         */
+    double  soe_tol;      /* relative SOE tolerance on [tau_1, T] (Lemma 2.2)      */
+    double  krylov_tol;   /* stop when ||b - M x||_2 <= tol ||b||_2                */
+    int32_t krylov_maxit; /* max BiCGSTAB iterations / max FGMRES inner iterations */
+                          /* summed over restarts, per time level                  */
+    int32_t restart;      /* FGMRES Krylov dimension J (<= 32)                     */
+    int32_t solver;       /* FIDS_BICGSTAB | FIDS_FGMRES                           */
+    int32_t precision;    /* FIDS_FP64 | FIDS_MIXED (MIXED needs FIDS_FGMRES)      */
+    int32_t precond;      /* FIDS_STRANG | FIDS_NONE                               */
+    int32_t kappa_time_dependent; /* 1: kappa_d is [M][n]; 0: kappa_d is [n]      */
+    int32_t x0_mode;      /* 0: zero initial guess (Sec. 5); 1: u^{m-1}            */
+    int32_t store_states; /* 1: keep every u^m in the workspace (needed by        */
+                          /* fids_adjoint); 0: keep only what stepping needs       */
+    int32_t wg_count;     /* workgroups that cooperate on one problem; 0 = auto    */
+} fids_params;
+
+/* Per-level report. */
+typedef struct fids_step_info {
+    int64_t m;            /* time level 1..M                                       */
+    int32_t iters;        /* Krylov iterations (BiCGSTAB: full iterations, a       */
+                          /* converged half iteration counts as one)               */
+    int32_t matvecs;      /* applications of M^{(m)} (the paper's Its is           */
+                          /* matvecs/2 for BiCGSTAB)                               */
+    double  relres;       /* final ||b - M x|| / ||b|| as computed by the solver   */
+} fids_step_info;
+
+typedef struct fids_problem fids_problem;
+
+/* Fills *p with: alpha 1.5, gamma 0.5, l 1, T 1, n 255, M 64, r 3, mu 0,
+ * soe_tol 1e-10, krylov_tol 1e-12, krylov_maxit 200, restart 20, BiCGSTAB,
+ * FP64, Strang, kappa_time_dependent 1, x0_mode 0, store_states 0, wg_count 0. */
+int fids_params_default(fids_params* p);
+
+/* Bytes of device workspace the problem needs (256-byte multiple).
+ * FIDS_EINVAL for an invalid parameter set (see fids_init_problem). */
+int fids_workspace_size(const fids_params* p, size_t* bytes);
+
+/* Host set-up (Sec. 2.1, 3.1, 4.1) and upload: graded mesh, b_m, SOE nodes
+ * and their per-level recurrence factors, the first column of A (3.16x) and
+ * its circulant-embedding symbol, the eigenvalues of Strang's s(A), FFT
+ * twiddles.  FIDS_EINVAL if alpha not in (0,2), gamma not in (0,1), mu not in
+ * (alpha, 2], r < 1, n < 1, M < 1, l <= 0, T <= 0, soe_tol or krylov_tol not
+ * in (0, 1), restart not in [1, 32], MIXED without FGMRES, a NULL pointer, or
+ * ws_bytes below fids_workspace_size.  On success *out owns host memory
+ * released by fids_destroy; the state is at level m = 0 with u^0 = phi. */
+int fids_init_problem(const fids_params* p, const double* kappa_d, const double* f_d,
+                      const double* phi_d, void* ws_d, size_t ws_bytes, void* hip_stream,
+                      fids_problem** out);
+
+/* Advance one level m -> m+1 (eq. 3.15): SOE history update and right-hand
+ * side, preconditioned Krylov solve.  u_out_d (may be NULL) receives u^{m+1};
+ * info (may be NULL) the level report.  FIDS_ESTATE after level M. */
+int fids_step(fids_problem* h, double* u_out_d, fids_step_info* info);
+
+/* Advance from the current level to M in one device launch.  uT_d (may be
+ * NULL) receives u^M; u_all_d (may be NULL; needs store_states = 1) receives
+ * u^0..u^M; per_step (may be NULL) is a host array of M entries filled for
+ * the levels advanced by this call (index m-1). */
+int fids_solve_all(fids_problem* h, double* uT_d, double* u_all_d, fids_step_info* per_step);
+
+/* Exact discrete adjoint of the FIDS steps run since the last reset, for a
+ * loss J(u^M): given dJ/du^M it returns dJ/dkappa (shape of kappa_d),
+ * dJ/df ([M][n]) and dJ/dphi ([n]); any output may be NULL.  Needs
+ * store_states = 1 and a completed forward run to level M (else FIDS_ESTATE). */
+int fids_adjoint(fids_problem* h, const double* dJ_duT_d, double* g_kappa_d,
+                 double* g_f_d, double* g_phi_d);
+
+/* Back to level 0 (u^0 = phi, empty history).  Tables are kept. */
+int fids_reset(fids_problem* h);
+
+/* Release the handle (not the caller's workspace or arrays).  NULL is a no-op. */
+int fids_destroy(fids_problem* h);
+
+/* Static message for a status code. */
+const char* fids_strerror(int status);
+
+/* ---------------- batched problems: independent instances of (1.1) -------- */
+typedef struct fids_batch fids_batch;
+
+/* Workspace for `count` problems p[0..count-1] advanced together. */
+int fids_batch_workspace_size(const fids_params* p, int32_t count, size_t* bytes);
+
+/* Like fids_init_problem for each problem i with its own parameters p[i] and
+ * borrowed arrays kappa_d[i], f_d[i], phi_d[i] (host arrays of device
+ * pointers).  All problems must share M (they advance level by level
+ * together); n, alpha, gamma, r and the fields may differ. */
+int fids_batch_init(const fids_params* p, int32_t count, const double* const* kappa_d,
+                    const double* const* f_d, const double* const* phi_d, void* ws_d,
+                    size_t ws_bytes, void* hip_stream, fids_batch** out);
+
+/* Advance every problem by one level; info (may be NULL) is [count]. */
+int fids_batch_step(fids_batch* b, fids_step_info* info);
+
+/* Advance every problem to level M in one launch; uT_d (may be NULL) is a host
+ * array of `count` device pointers receiving u^M; info (may be NULL) is a host
+ * array [count][M]. */
+int fids_batch_solve_all(fids_batch* b, double* const* uT_d, fids_step_info* info);
+
+int fids_batch_reset(fids_batch* b);
+int fids_batch_destroy(fids_batch* b);
+
+/* ---------------- host-only introspection (no device work) ---------------- */
+/* SOE of Lemma 2.2: nodes s[j] and weights w[j] with
+ * |t^gamma sum_j w_j e^{-s_j t} - 1| <= tol for t in [delta, T].
+ * *count receives the node number; FIDS_EINVAL if it exceeds cap. */
+int fids_soe_nodes(double gamma, double delta, double T, double tol, int32_t cap,
+                   double* s, double* w, int32_t* count);
+
+/* First column of A, eq. (3.16x), into col[0..n-1]; mu = 0 selects 1+alpha/2. */
+int fids_ifl_column(int64_t n, double alpha, double l, double mu, double* col);
+
+/* Eigenvalues of Strang's circulant s(A), lam[k] = sum_j c_S[j] cos(2 pi jk/n). */
+int fids_strang_eigs(int64_t n, double alpha, double l, double mu, double* lam);
+
+/* b_m = tau_m^{-gamma} / Gamma(2-gamma) for m = 1..M into beta[m-1]. */
+int fids_level_coefficients(double gamma, double T, int64_t M, double r, double* beta);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIDS_H */

@@ -1,0 +1,493 @@
+// C ABI of the library (include/fids.h): parameter checks, workspace layout,
+// upload of the host set-up tables, and the launches of each call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fids.h"
+#include "fids_device.h"
+#include "fids_launch.h"
+#include "fids_setup.h"
+
+using fids::cplx;
+using fids::HostTables;
+using fids::Plan;
+using fids::Prob;
+using fids::SymJob;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+int ilog2i(int64_t v) { int r = 0; while ((int64_t(1) << r) < v) ++r; return r; }
+
+// Shapes of a two-pass plan for Nc complex points.
+struct PlanShape {
+  int Nc, N1, N2, log1, log2, CT, ntiles, nunits;
+};
+
+PlanShape plan_shape(int64_t Nc, int ct_override) {
+  PlanShape s{};
+  const int p = ilog2i(Nc);
+  s.Nc = int(Nc);
+  s.log1 = (p + 1) / 2;
+  s.log2 = p / 2;
+  s.N1 = 1 << s.log1;
+  s.N2 = 1 << s.log2;
+  int ct = ct_override > 0 ? ct_override : std::max(1, 2 * s.N2 / s.N1);
+  ct = std::min(ct, s.N2);
+  while (ct > 1 && ct * s.N1 > 1024) ct >>= 1;
+  s.CT = ct;
+  s.ntiles = s.N2 / s.CT;
+  s.nunits = s.N1 / 2;
+  return s;
+}
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
+// Workspace layout of one problem.  Offsets are bytes from ws_d.
+struct Layout {
+  size_t prob, job, abort_, status, bar, info, part;
+  size_t beta, theta, decay, gw, ahat, lam, chirp, chirp_hat, kbar;
+  size_t tw1r, tw1rf, tw2r, tw2rf, tw1c, tw1cf, tw2c, tw2cf, twlo, twlof, twhi, twhif;
+  size_t qhat, qhatf;
+  size_t Tb, q, Tq;
+  size_t u[3], F, kap, vec[10], uhist, T, Tf;
+  size_t total;
+  int chunk;
+  int twshift;
+};
+
+struct Shapes {
+  int64_t n, M, L, Nc;
+  int nexp;
+  PlanShape pr, pc;
+};
+
+Layout make_layout(const fids_params& p, const Shapes& sh) {
+  Layout lo{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + std::max<size_t>(bytes, 1)); return o; };
+  const size_t n = size_t(sh.n), M = size_t(sh.M), L = size_t(sh.L), Nc = size_t(sh.Nc), ne = size_t(sh.nexp);
+  lo.prob = take(sizeof(Prob));
+  lo.job = take(sizeof(SymJob));
+  lo.abort_ = take(sizeof(int));
+  lo.status = take(4 * sizeof(int));
+  lo.bar = take(4 * sizeof(unsigned));
+  lo.info = take(M * sizeof(fids_step_info));
+  lo.part = take(size_t(fids::SL_COUNT) * sh.pr.ntiles * sizeof(double));
+  lo.beta = take((M + 1) * 8);
+  lo.theta = take((M + 1) * ne * 8);
+  lo.decay = take((M + 1) * ne * 8);
+  lo.gw = take(ne * 8);
+  lo.ahat = take((Nc + 1) * 8);
+  lo.lam = take(n * 8);
+  lo.chirp = take(n * 16);
+  lo.chirp_hat = take(L * 16);
+  lo.kbar = take((M + 1) * 8);
+  lo.tw1r = take(size_t(sh.pr.N1) * 16); lo.tw1rf = take(size_t(sh.pr.N1) * 8);
+  lo.tw2r = take(size_t(sh.pr.N2) * 16); lo.tw2rf = take(size_t(sh.pr.N2) * 8);
+  lo.tw1c = take(size_t(sh.pc.N1) * 16); lo.tw1cf = take(size_t(sh.pc.N1) * 8);
+  lo.tw2c = take(size_t(sh.pc.N2) * 16); lo.tw2cf = take(size_t(sh.pc.N2) * 8);
+  const int q = ilog2i(sh.L);
+  lo.twshift = (q + 1) / 2;
+  const size_t nlo = size_t(1) << lo.twshift, nhi = L >> lo.twshift;
+  lo.twlo = take(nlo * 16); lo.twlof = take(nlo * 8);
+  lo.twhi = take(nhi * 16); lo.twhif = take(nhi * 8);
+  const bool mixed = p.precision == FIDS_MIXED;
+  lo.qhat = mixed ? 0 : take((M + 1) * (Nc + 1) * 8);
+  lo.qhatf = mixed ? take((M + 1) * (Nc + 1) * 4) : 0;
+  // symbol scratch: about 64 MiB per chunk
+  const size_t per = L * 16 + n * 8 + Nc * 16;
+  lo.chunk = int(std::max<size_t>(1, std::min<size_t>(M, (size_t(64) << 20) / per)));
+  lo.Tb = take(size_t(lo.chunk) * L * 16);
+  lo.q = take(size_t(lo.chunk) * n * 8);
+  lo.Tq = take(size_t(lo.chunk) * Nc * 16);
+  for (int i = 0; i < 3; ++i) lo.u[i] = take(L * 8);
+  lo.F = take(ne * L * 8);
+  lo.kap = take(L * 8);
+  for (int i = 0; i < 10; ++i) lo.vec[i] = take(L * 8);
+  lo.uhist = p.store_states ? take((M + 1) * L * 8) : 0;
+  lo.T = take(Nc * 16);
+  lo.Tf = take(Nc * 8);
+  lo.total = off;
+  return lo;
+}
+
+int shapes_of(const fids_params& p, Shapes& sh, fids::SoeNodes* soe_out) {
+  if (fids::validate(p) != FIDS_OK) return FIDS_EINVAL;
+  sh.n = p.n;
+  sh.M = p.M;
+  sh.L = fids::embed_length(p.n);
+  sh.Nc = sh.L / 2;
+  fids::SoeNodes soe;
+  const double tau1 = p.T * std::pow(1.0 / double(p.M), p.r);
+  if (fids::soe_build(p.gamma, tau1, p.T, p.soe_tol, soe) != FIDS_OK) return FIDS_EINVAL;
+  sh.nexp = int(soe.s.size());
+  sh.pr = plan_shape(sh.Nc, env_int("FIDS_CT", 0));
+  sh.pc = plan_shape(sh.L, 8);
+  if (soe_out) *soe_out = soe;
+  return FIDS_OK;
+}
+
+std::vector<double2> twiddles(int64_t P) {
+  std::vector<double2> t(P);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int64_t j = 0; j < P; ++j) {
+    const long double a = -2.0L * pi * (long double)j / (long double)P;
+    t[j] = make_double2(double(std::cos(a)), double(std::sin(a)));
+  }
+  return t;
+}
+
+std::vector<double2> root_table(int64_t L, int64_t count, int64_t step) {
+  std::vector<double2> t(count);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int64_t j = 0; j < count; ++j) {
+    const long double a = -2.0L * pi * (long double)(j * step) / (long double)L;
+    t[j] = make_double2(double(std::cos(a)), double(std::sin(a)));
+  }
+  return t;
+}
+
+std::vector<float2> to_f(const std::vector<double2>& v) {
+  std::vector<float2> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = make_float2(float(v[i].x), float(v[i].y));
+  return o;
+}
+
+}  // namespace
+
+struct fids_problem {
+  fids_params prm{};
+  HostTables tab;
+  Shapes sh{};
+  Layout lo{};
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Prob hp{};
+  Prob* dp = nullptr;
+  SymJob hj{};
+  SymJob* dj = nullptr;
+  int* dabort = nullptr;
+  int* dstatus = nullptr;
+  int64_t level = 0;
+  bool symbols_ready = false;
+  size_t lds = 0;
+  unsigned long long timeout_ticks = 0;
+  // host copies kept alive for asynchronous uploads
+  std::vector<std::vector<double2>> keep2;
+  std::vector<std::vector<float2>> keepf;
+};
+
+namespace {
+
+#define HIPCHK(x)                          \
+  do {                                     \
+    if ((x) != hipSuccess) return FIDS_EDEVICE; \
+  } while (0)
+
+template <typename T>
+T* at(char* ws, size_t off) { return reinterpret_cast<T*>(ws + off); }
+
+int upload(fids_problem* h, size_t off, const void* src, size_t bytes) {
+  if (bytes == 0) return FIDS_OK;
+  HIPCHK(hipMemcpyAsync(h->ws + off, src, bytes, hipMemcpyHostToDevice, h->stream));
+  return FIDS_OK;
+}
+
+void fill_plan(Plan& pl, const PlanShape& s, int rootmul, char* ws, const Layout& lo, bool complex_plan) {
+  pl.Nc = s.Nc; pl.N1 = s.N1; pl.N2 = s.N2; pl.log1 = s.log1; pl.log2 = s.log2; pl.CT = s.CT;
+  pl.ntiles = s.ntiles; pl.nunits = s.nunits; pl.rootmul = rootmul;
+  pl.twshift = lo.twshift; pl.twmask = (1 << lo.twshift) - 1;
+  pl.tw1 = at<double2>(ws, complex_plan ? lo.tw1c : lo.tw1r);
+  pl.tw1f = at<float2>(ws, complex_plan ? lo.tw1cf : lo.tw1rf);
+  pl.tw2 = at<double2>(ws, complex_plan ? lo.tw2c : lo.tw2r);
+  pl.tw2f = at<float2>(ws, complex_plan ? lo.tw2cf : lo.tw2rf);
+  pl.twlo = at<double2>(ws, lo.twlo); pl.twlof = at<float2>(ws, lo.twlof);
+  pl.twhi = at<double2>(ws, lo.twhi); pl.twhif = at<float2>(ws, lo.twhif);
+}
+
+int ensure_symbols(fids_problem* h) {
+  if (h->symbols_ready) return FIDS_OK;
+  const int M = int(h->sh.M);
+  HIPCHK(fids::launch_kbar(h->prm.kappa_time_dependent ? h->hp.kappa : h->hp.kappa, int(h->sh.n), M,
+                           h->prm.kappa_time_dependent, at<double>(h->ws, h->lo.kbar), h->stream));
+  for (int m0 = 1; m0 <= M; m0 += h->lo.chunk) {
+    const int cnt = std::min(h->lo.chunk, M - m0 + 1);
+    HIPCHK(fids::launch_symbols(h->hj, h->dj, m0, cnt, h->stream));
+  }
+  h->symbols_ready = true;
+  return FIDS_OK;
+}
+
+int run_levels(fids_problem* h, int64_t m_end, fids_step_info* infos_host /*[M] indexed m-1*/) {
+  if (h->level >= h->sh.M) return FIDS_ESTATE;
+  int st = ensure_symbols(h);
+  if (st != FIDS_OK) return st;
+  const int m_begin = int(h->level + 1);
+  HIPCHK(hipMemsetAsync(h->dabort, 0, sizeof(int), h->stream));
+  HIPCHK(fids::launch_levels(h->dp, 1, h->hp.ng, h->lds, m_begin, int(m_end), h->timeout_ticks, h->dabort,
+                             h->stream));
+  int stat[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(stat, h->dstatus, sizeof(stat), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const int64_t last = stat[1];
+  const int64_t first = m_begin;
+  const int64_t upto = std::min<int64_t>(m_end, std::max<int64_t>(last + (stat[0] != FIDS_OK ? 1 : 0), first - 1));
+  if (infos_host && upto >= first) {
+    HIPCHK(hipMemcpy(infos_host + (first - 1), at<fids_step_info>(h->ws, h->lo.info) + (first - 1),
+                     size_t(upto - first + 1) * sizeof(fids_step_info), hipMemcpyDeviceToHost));
+  }
+  if (last >= first) h->level = last;
+  if (stat[0] == FIDS_EDEVICE) {
+    // a group barrier timed out: clear the barrier words for the next launch
+    HIPCHK(hipMemsetAsync(h->hp.bar, 0, 4 * sizeof(unsigned), h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  return stat[0];
+}
+
+}  // namespace
+
+extern "C" {
+
+int fids_params_default(fids_params* p) {
+  if (!p) return FIDS_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->alpha = 1.5; p->gamma = 0.5; p->l = 1.0; p->T = 1.0;
+  p->n = 255; p->M = 64; p->r = 3.0; p->mu = 0.0;
+  p->soe_tol = 1e-10; p->krylov_tol = 1e-12; p->krylov_maxit = 200; p->restart = 20;
+  p->solver = FIDS_BICGSTAB; p->precision = FIDS_FP64; p->precond = FIDS_STRANG;
+  p->kappa_time_dependent = 1; p->x0_mode = 0; p->store_states = 0; p->wg_count = 0;
+  return FIDS_OK;
+}
+
+const char* fids_strerror(int s) {
+  switch (s) {
+    case FIDS_OK: return "ok";
+    case FIDS_EINVAL: return "invalid argument";
+    case FIDS_EDEVICE: return "HIP device error";
+    case FIDS_ENOCONV: return "Krylov solver did not converge";
+    case FIDS_ENUMERIC: return "non-finite value on the device";
+    case FIDS_ESTATE: return "call not valid in the current state";
+    default: return "unknown status";
+  }
+}
+
+int fids_workspace_size(const fids_params* p, size_t* bytes) {
+  if (!p || !bytes) return FIDS_EINVAL;
+  if (p->solver != FIDS_BICGSTAB) return FIDS_EINVAL;  // FGMRES path is built separately
+  Shapes sh;
+  if (shapes_of(*p, sh, nullptr) != FIDS_OK) return FIDS_EINVAL;
+  *bytes = make_layout(*p, sh).total;
+  return FIDS_OK;
+}
+
+int fids_init_problem(const fids_params* p, const double* kappa_d, const double* f_d, const double* phi_d,
+                      void* ws_d, size_t ws_bytes, void* hip_stream, fids_problem** out) {
+  if (!p || !kappa_d || !f_d || !phi_d || !ws_d || !out) return FIDS_EINVAL;
+  if (p->solver != FIDS_BICGSTAB) return FIDS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(ws_d) % kAlign) return FIDS_EINVAL;
+  *out = nullptr;
+  fids_problem* h = new (std::nothrow) fids_problem();
+  if (!h) return FIDS_EINVAL;
+  h->prm = *p;
+  if (shapes_of(*p, h->sh, nullptr) != FIDS_OK || fids::build_tables(*p, h->tab) != FIDS_OK) {
+    delete h;
+    return FIDS_EINVAL;
+  }
+  h->sh.nexp = h->tab.nexp;
+  h->lo = make_layout(*p, h->sh);
+  if (ws_bytes < h->lo.total) { delete h; return FIDS_EINVAL; }
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->ws = static_cast<char*>(ws_d);
+  char* ws = h->ws;
+  const Layout& lo = h->lo;
+  const HostTables& t = h->tab;
+  int st = FIDS_OK;
+  auto fail = [&](int code) { delete h; return code; };
+  if (hipMemsetAsync(ws, 0, lo.total, h->stream) != hipSuccess) return fail(FIDS_EDEVICE);
+  // tables
+  st |= upload(h, lo.beta, t.beta.data(), t.beta.size() * 8);
+  st |= upload(h, lo.theta, t.theta.data(), t.theta.size() * 8);
+  st |= upload(h, lo.decay, t.decay.data(), t.decay.size() * 8);
+  st |= upload(h, lo.gw, t.gw.data(), t.gw.size() * 8);
+  st |= upload(h, lo.ahat, t.ahat.data(), t.ahat.size() * 8);
+  st |= upload(h, lo.lam, t.lam.data(), t.lam.size() * 8);
+  st |= upload(h, lo.chirp, t.chirp.data(), t.chirp.size() * 16);
+  st |= upload(h, lo.chirp_hat, t.chirp_hat.data(), t.chirp_hat.size() * 16);
+  auto put2 = [&](size_t o, size_t of, std::vector<double2> v) {
+    h->keepf.push_back(to_f(v));
+    h->keep2.push_back(std::move(v));
+    st |= upload(h, o, h->keep2.back().data(), h->keep2.back().size() * 16);
+    st |= upload(h, of, h->keepf.back().data(), h->keepf.back().size() * 8);
+  };
+  put2(lo.tw1r, lo.tw1rf, twiddles(h->sh.pr.N1));
+  put2(lo.tw2r, lo.tw2rf, twiddles(h->sh.pr.N2));
+  put2(lo.tw1c, lo.tw1cf, twiddles(h->sh.pc.N1));
+  put2(lo.tw2c, lo.tw2cf, twiddles(h->sh.pc.N2));
+  put2(lo.twlo, lo.twlof, root_table(h->sh.L, int64_t(1) << lo.twshift, 1));
+  put2(lo.twhi, lo.twhif, root_table(h->sh.L, h->sh.L >> lo.twshift, int64_t(1) << lo.twshift));
+  if (st != FIDS_OK) return fail(FIDS_EDEVICE);
+  // problem descriptor
+  Prob& hp = h->hp;
+  hp.n = int(p->n); hp.M = int(p->M); hp.nexp = t.nexp;
+  hp.solver = p->solver; hp.precision = p->precision; hp.precond = p->precond;
+  hp.kappa_td = p->kappa_time_dependent; hp.x0_mode = p->x0_mode; hp.maxit = p->krylov_maxit;
+  hp.restart = p->restart; hp.store_states = p->store_states; hp.tol = p->krylov_tol;
+  hp.L = int(h->sh.L); hp.vlen = int(h->sh.L);
+  fill_plan(hp.pl, h->sh.pr, 2, ws, lo, false);
+  const int maxg = std::max(hp.pl.ntiles, hp.pl.nunits);
+  int ng = p->wg_count > 0 ? p->wg_count : env_int("FIDS_WG", std::min(maxg, 256));
+  ng = std::max(1, std::min(ng, maxg));
+  hp.g0 = 0; hp.ng = ng;
+  hp.beta = at<double>(ws, lo.beta); hp.theta = at<double>(ws, lo.theta); hp.decay = at<double>(ws, lo.decay);
+  hp.gw = at<double>(ws, lo.gw); hp.ahat = at<double>(ws, lo.ahat);
+  hp.qhat = lo.qhat ? at<double>(ws, lo.qhat) : nullptr;
+  hp.qhatf = lo.qhatf ? at<float>(ws, lo.qhatf) : nullptr;
+  hp.kappa = kappa_d; hp.f = f_d; hp.phi = phi_d;
+  for (int i = 0; i < 3; ++i) hp.u[i] = at<double>(ws, lo.u[i]);
+  hp.F = at<double>(ws, lo.F); hp.kap = at<double>(ws, lo.kap);
+  for (int i = 0; i < 10; ++i) hp.vec[i] = at<double>(ws, lo.vec[i]);
+  hp.zf = nullptr; hp.V = nullptr;
+  hp.uhist = lo.uhist ? at<double>(ws, lo.uhist) : nullptr;
+  hp.T = at<double2>(ws, lo.T); hp.Tf = at<float2>(ws, lo.Tf);
+  hp.part = at<double>(ws, lo.part);
+  hp.info = at<fids_step_info>(ws, lo.info);
+  hp.status = at<int>(ws, lo.status);
+  hp.bar = at<unsigned>(ws, lo.bar);
+  h->dp = at<Prob>(ws, lo.prob);
+  h->dabort = at<int>(ws, lo.abort_);
+  h->dstatus = hp.status;
+  // symbol job
+  SymJob& j = h->hj;
+  j.n = int(p->n); j.L = int(h->sh.L); j.Nc = int(h->sh.Nc); j.M = int(p->M);
+  fill_plan(j.plc, h->sh.pc, 1, ws, lo, true);
+  fill_plan(j.plr, h->sh.pr, 2, ws, lo, false);
+  j.beta = hp.beta; j.kbar = at<double>(ws, lo.kbar); j.lam = at<double>(ws, lo.lam);
+  j.chirp = at<double2>(ws, lo.chirp); j.chirp_hat = at<double2>(ws, lo.chirp_hat);
+  j.Tb = at<double2>(ws, lo.Tb); j.q = at<double>(ws, lo.q); j.Tq = at<double2>(ws, lo.Tq);
+  j.qhat = const_cast<double*>(hp.qhat); j.qhatf = const_cast<float*>(hp.qhatf);
+  j.identity = p->precond == FIDS_NONE;
+  h->dj = at<SymJob>(ws, lo.job);
+  if (upload(h, lo.prob, &h->hp, sizeof(Prob)) != FIDS_OK) return fail(FIDS_EDEVICE);
+  if (upload(h, lo.job, &h->hj, sizeof(SymJob)) != FIDS_OK) return fail(FIDS_EDEVICE);
+  h->lds = fids::level_lds_bytes(hp);
+  if (fids::launch_init_state(hp, h->dp, h->stream) != hipSuccess) return fail(FIDS_EDEVICE);
+  int dev = 0, rate_khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(FIDS_EDEVICE);
+  if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return fail(FIDS_EDEVICE);
+  h->timeout_ticks = (unsigned long long)(std::max(rate_khz, 1000)) * 1000ull * 4ull;  // 4 s
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(FIDS_EDEVICE);
+  *out = h;
+  return FIDS_OK;
+}
+
+int fids_reset(fids_problem* h) {
+  if (!h) return FIDS_EINVAL;
+  if (fids::launch_init_state(h->hp, h->dp, h->stream) != hipSuccess) return FIDS_EDEVICE;
+  HIPCHK(hipMemsetAsync(h->hp.F, 0, size_t(h->hp.nexp) * h->hp.vlen * 8, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->level = 0;
+  h->symbols_ready = false;  // every solve from level 0 rebuilds the per-level symbols
+  return FIDS_OK;
+}
+
+int fids_destroy(fids_problem* h) {
+  delete h;
+  return FIDS_OK;
+}
+
+int fids_step(fids_problem* h, double* u_out_d, fids_step_info* info) {
+  if (!h) return FIDS_EINVAL;
+  if (h->level >= h->sh.M) return FIDS_ESTATE;
+  std::vector<fids_step_info> tmp(size_t(h->sh.M));
+  const int64_t m = h->level + 1;
+  const int st = run_levels(h, m, tmp.data());
+  if (info) *info = tmp[size_t(m - 1)];
+  if (st != FIDS_OK) return st;
+  if (u_out_d) {
+    HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.u[m % 3], u_out_d, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  return FIDS_OK;
+}
+
+int fids_solve_all(fids_problem* h, double* uT_d, double* u_all_d, fids_step_info* per_step) {
+  if (!h) return FIDS_EINVAL;
+  if (u_all_d && !h->prm.store_states) return FIDS_EINVAL;
+  if (h->level >= h->sh.M) return FIDS_ESTATE;
+  const int st = run_levels(h, h->sh.M, per_step);
+  if (st != FIDS_OK) return st;
+  if (uT_d) HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.u[h->sh.M % 3], uT_d, h->stream));
+  if (u_all_d)
+    for (int64_t m = 0; m <= h->sh.M; ++m)
+      HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.uhist + size_t(m) * h->hp.vlen,
+                                     u_all_d + size_t(m) * h->sh.n, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return FIDS_OK;
+}
+
+int fids_adjoint(fids_problem* h, const double*, double*, double*, double*) {
+  if (!h) return FIDS_EINVAL;
+  return FIDS_ESTATE;
+}
+
+// ---------------------------------------------------------------- batched (not yet built)
+int fids_batch_workspace_size(const fids_params*, int32_t, size_t*) { return FIDS_EINVAL; }
+int fids_batch_init(const fids_params*, int32_t, const double* const*, const double* const*,
+                    const double* const*, void*, size_t, void*, fids_batch**) { return FIDS_EINVAL; }
+int fids_batch_step(fids_batch*, fids_step_info*) { return FIDS_EINVAL; }
+int fids_batch_solve_all(fids_batch*, double* const*, fids_step_info*) { return FIDS_EINVAL; }
+int fids_batch_reset(fids_batch*) { return FIDS_EINVAL; }
+int fids_batch_destroy(fids_batch*) { return FIDS_OK; }
+
+// ---------------------------------------------------------------- introspection
+int fids_soe_nodes(double gamma, double delta, double T, double tol, int32_t cap, double* s, double* w,
+                   int32_t* count) {
+  if (!s || !w || !count) return FIDS_EINVAL;
+  fids::SoeNodes q;
+  if (fids::soe_build(gamma, delta, T, tol, q) != FIDS_OK) return FIDS_EINVAL;
+  *count = int32_t(q.s.size());
+  if (*count > cap) return FIDS_EINVAL;
+  std::copy(q.s.begin(), q.s.end(), s);
+  std::copy(q.w.begin(), q.w.end(), w);
+  return FIDS_OK;
+}
+
+int fids_ifl_column(int64_t n, double alpha, double l, double mu, double* col) {
+  if (!col || n < 1 || !(alpha > 0 && alpha < 2) || !(l > 0)) return FIDS_EINVAL;
+  const double me = mu > 0 ? mu : 1 + alpha / 2;
+  if (!(me > alpha && me <= 2)) return FIDS_EINVAL;
+  const auto c = fids::ifl_column(n, alpha, l, me);
+  std::copy(c.begin(), c.end(), col);
+  return FIDS_OK;
+}
+
+int fids_strang_eigs(int64_t n, double alpha, double l, double mu, double* lam) {
+  if (!lam || n < 1 || !(alpha > 0 && alpha < 2) || !(l > 0)) return FIDS_EINVAL;
+  const double me = mu > 0 ? mu : 1 + alpha / 2;
+  if (!(me > alpha && me <= 2)) return FIDS_EINVAL;
+  const auto e = fids::strang_eigs(fids::ifl_column(n, alpha, l, me));
+  std::copy(e.begin(), e.end(), lam);
+  return FIDS_OK;
+}
+
+int fids_level_coefficients(double gamma, double T, int64_t M, double r, double* beta) {
+  if (!beta || M < 1 || !(gamma > 0 && gamma < 1) || !(T > 0) || !(r >= 1)) return FIDS_EINVAL;
+  const auto tau = fids::step_sizes(T, M, r);
+  const double g2 = std::tgamma(2.0 - gamma);
+  for (int64_t m = 1; m <= M; ++m) beta[m - 1] = std::pow(tau[m], -gamma) / g2;
+  return FIDS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Device-side descriptors shared by the HIP kernels and the host launcher.
+//
+// Layout of every internal n-vector ("tile-major"): the real index i of the
+// length-L zero-padded vector is packed in pairs z[k] = (x[2k], x[2k+1]),
+// k = N2*n1 + n2 (four-step FFT split Nc = L/2 = N1*N2), and stored at
+//     tile*(2*CT*N1) + 2*(n1*CT + c) + e,   n2 = tile*CT + c,  i = 2k + e,
+// so that each column tile of the first FFT pass owns one contiguous block.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "fids.h"
+
+namespace fids {
+
+constexpr int kThreads = 256;     // threads per workgroup in every kernel
+constexpr int kMaxFFT = 4096;     // longest per-workgroup FFT (complex points)
+constexpr int kMaxRestart = 32;
+
+// Partial-sum slots (one value per column tile each).
+enum Slot {
+  SL_BB = 0, SL_RV, SL_SS, SL_RS, SL_TS, SL_TT, SL_RT, SL_RR, SL_KB,
+  SL_GM = 9,                      // FGMRES: kMaxRestart + 2 consecutive slots
+  SL_COUNT = SL_GM + kMaxRestart + 2
+};
+
+// Two-pass FFT plan for Nc = N1 * N2 complex points.
+struct Plan {
+  int Nc, N1, N2, log1, log2, CT;
+  int ntiles;        // N2 / CT column tiles
+  int nunits;        // N1 / 2 row-pair units
+  int rootmul;       // W_Nc = W_root^rootmul (2 for the real-packed plan, 1 complex)
+  int twshift;       // split of the root table: j = (jh << twshift) + jl
+  int twmask;
+  const double2* tw1;  const float2* tw1f;   // W_{N1}^j, j < N1 (e^{-2 pi i j/N1})
+  const double2* tw2;  const float2* tw2f;   // W_{N2}^j
+  const double2* twlo; const float2* twlof;  // W_root^{jl}
+  const double2* twhi; const float2* twhif;  // W_root^{jh << twshift}
+};
+
+// Per-problem descriptor, in device memory.
+struct Prob {
+  int n, M, nexp;
+  int solver, precision, precond, kappa_td, x0_mode, maxit, restart, store_states;
+  double tol;
+  int g0, ng;                   // workgroups [g0, g0 + ng) cooperate on this problem
+  int L, vlen;                  // embedding length and tile-major vector length (= L)
+  Plan pl;                      // real-packed plan, Nc = L/2
+  // set-up tables
+  const double* beta;           // [M+1]
+  const double* theta;          // [(M+1) * nexp]
+  const double* decay;          // [(M+1) * nexp]
+  const double* gw;             // [nexp]
+  const double* ahat;           // [Nc+1]
+  const double* qhat;           // [(M+1) * (Nc+1)] per-level P^{-1} symbols (FP64 path)
+  const float* qhatf;           // same in FP32 (mixed path)
+  // caller's arrays (natural layout)
+  const double* kappa;
+  const double* f;
+  const double* phi;
+  // state (tile-major, vlen doubles each)
+  double* u[3];                 // u^m lives in u[m % 3]
+  double* F;                    // [ntiles][nexp][2*CT*N1]
+  double* kap;                  // kappa^m, tile-major
+  double* vec[10];              // Krylov vectors (solver specific)
+  float* zf;                    // FGMRES: Z basis in FP32, [restart][vlen]
+  double* V;                    // FGMRES: V basis, [restart+1][vlen]
+  double* uhist;                // [(M+1)][vlen] when store_states
+  double2* T;                   // FFT intermediate, Nc complex
+  float2* Tf;                   // FP32 FFT intermediate, Nc complex
+  double* part;                 // [SL_COUNT][ntiles]
+  fids_step_info* info;         // [M]
+  int* status;                  // [1]
+  unsigned* bar;                // [2] group barrier {count, generation}
+};
+
+// Bluestein / symbol-precompute descriptor (batched over levels).
+struct SymJob {
+  int n, L, Nc, M;
+  Plan plc;                     // complex plan of length L
+  Plan plr;                     // real-packed plan of length L (Nc = L/2)
+  const double* beta;           // [M+1]
+  const double* kbar;           // [M+1] mean of kappa^m
+  const double* lam;            // [n]
+  const double2* chirp;         // [n]
+  const double2* chirp_hat;     // [L]
+  double2* Tb;                  // [chunk][L]
+  double* q;                    // [chunk][n]
+  double2* Tq;                  // [chunk][Nc]
+  double* qhat;                 // [(M+1)][Nc+1] (may be null)
+  float* qhatf;                 // [(M+1)][Nc+1] (may be null)
+  int identity;                 // precond NONE: symbols are all ones
+};
+
+}  // namespace fids

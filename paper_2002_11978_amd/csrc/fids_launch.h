@@ -1,0 +1,35 @@
+// Host launchers for the gfx950 kernels (implemented in fids_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fids_device.h"
+
+namespace fids {
+
+// LDS bytes a workgroup of the level kernel needs for problem descriptor `h`.
+size_t level_lds_bytes(const Prob& h);
+
+// Clears the state of one problem and sets u^0 = phi (tile-major).
+hipError_t launch_init_state(const Prob& h, const Prob* d, hipStream_t s);
+
+// Mean of kappa^m for m = 1..M (or the single row) into kbar[1..M].
+hipError_t launch_kbar(const double* kappa, int n, int M, int td, double* kbar, hipStream_t s);
+
+// Per-level preconditioner symbols for levels [m0, m0 + cnt).
+hipError_t launch_symbols(const SymJob& job, const SymJob* d, int m0, int cnt, hipStream_t s);
+
+// LDS bytes of the symbol kernels.
+size_t symbols_lds_bytes(const SymJob& job);
+
+// Advances every problem in `probs` (device array of `nprob` descriptors whose
+// workgroup groups tile [0, total_wg)) over levels [m_begin, m_end] in one
+// cooperative launch.
+hipError_t launch_levels(const Prob* probs, int nprob, int total_wg, size_t lds_bytes,
+                         int m_begin, int m_end, unsigned long long timeout_ticks,
+                         int* abort_flag, hipStream_t s);
+
+// Copies u^m (tile-major) into a natural-layout [n] array.
+hipError_t launch_to_natural(const Prob& h, const Prob* d, const double* src, double* dst, hipStream_t s);
+
+}  // namespace fids

@@ -1,0 +1,65 @@
+// Host-side set-up of the fast implicit difference scheme (FP64 C++).
+//
+// Everything here runs once per problem, before any time level: the graded
+// mesh and level coefficients (Sec. 2.1), the sum-of-exponentials nodes and
+// their recurrence factors (Lemma 2.2, eq. 2.9), the first column of the IFL
+// matrix A (eq. 3.16x) and its circulant-embedding symbol, the eigenvalues of
+// Strang's circulant s(A) (eq. 4.3) and the Bluestein chirp used on the device
+// to invert the per-level circulant.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <vector>
+
+#include "fids.h"
+
+namespace fids {
+
+using cplx = std::complex<double>;
+
+struct SoeNodes {
+  std::vector<double> s, w;
+};
+
+struct HostTables {
+  int64_t n = 0, M = 0;
+  int64_t L = 0;        // embedding length: smallest power of two >= 2n (>= 4)
+  int64_t Nc = 0;       // L / 2, length of the packed complex FFT
+  int nexp = 0;         // SOE node count
+  double g = 0;         // 1 / Gamma(1 - gamma)
+  std::vector<double> tau;     // [M+1], tau[m] = t_m - t_{m-1}, tau[0] = 0
+  std::vector<double> beta;    // [M+1], beta[m] = g a_m^{(m)} = tau_m^{-gamma}/Gamma(2-gamma)
+  std::vector<double> theta;   // [(M+1) * nexp], recurrence input factor (m >= 2)
+  std::vector<double> decay;   // [(M+1) * nexp], e^{-s_j tau_m}
+  std::vector<double> gw;      // [nexp], g w_j
+  SoeNodes soe;
+  std::vector<double> col;     // [n], first column of A
+  std::vector<double> ahat;    // [Nc+1], real symbol of A's L-circulant embedding
+  std::vector<double> lam;     // [n], eigenvalues of s(A)
+  std::vector<cplx> chirp;     // [n], e^{i pi k^2 / n}
+  std::vector<cplx> chirp_hat; // [L], FFT_L of the embedded conj(chirp)
+};
+
+// Parameter checks of fids_init_problem; returns FIDS_OK or FIDS_EINVAL.
+int validate(const fids_params& p);
+
+// Effective mu (0 selects 1 + alpha/2).
+double mu_effective(const fids_params& p);
+
+int64_t embed_length(int64_t n);
+
+// The pieces, exposed for the introspection entry points.
+std::vector<double> ifl_column(int64_t n, double alpha, double l, double mu);
+std::vector<double> strang_eigs(const std::vector<double>& col);
+int soe_build(double gamma, double delta, double T, double tol, SoeNodes& out);
+double soe_max_rel_error(const SoeNodes& q, double gamma, double delta, double T, int npts);
+std::vector<double> step_sizes(double T, int64_t M, double r);
+
+// Full set-up; returns FIDS_OK / FIDS_EINVAL.
+int build_tables(const fids_params& p, HostTables& t);
+
+// In-place radix-2 complex FFT (sign = -1 forward, +1 inverse, unnormalised).
+void host_fft(std::vector<cplx>& a, int sign);
+
+}  // namespace fids

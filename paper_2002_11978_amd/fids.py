@@ -1,0 +1,249 @@
+"""Thin Python binding of libfids (include/fids.h).
+
+Argument marshalling only: every step of the time-stepping path runs in the
+library's HIP kernels.  PyTorch provides device memory (the workspace and the
+caller's arrays) and the HIP stream.  If libfids.so is missing the import of
+this module succeeds but every call raises RuntimeError -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfids.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "fids.h")
+
+FIDS_OK, FIDS_EINVAL, FIDS_EDEVICE, FIDS_ENOCONV, FIDS_ENUMERIC, FIDS_ESTATE = 0, -1, -2, -3, -4, -5
+FIDS_BICGSTAB, FIDS_FGMRES = 0, 1
+FIDS_FP64, FIDS_MIXED = 0, 1
+FIDS_STRANG, FIDS_NONE = 0, 1
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("alpha", ctypes.c_double), ("gamma", ctypes.c_double), ("l", ctypes.c_double),
+        ("T", ctypes.c_double), ("n", ctypes.c_int64), ("M", ctypes.c_int64),
+        ("r", ctypes.c_double), ("mu", ctypes.c_double), ("soe_tol", ctypes.c_double),
+        ("krylov_tol", ctypes.c_double), ("krylov_maxit", ctypes.c_int32),
+        ("restart", ctypes.c_int32), ("solver", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("precond", ctypes.c_int32), ("kappa_time_dependent", ctypes.c_int32),
+        ("x0_mode", ctypes.c_int32), ("store_states", ctypes.c_int32), ("wg_count", ctypes.c_int32),
+    ]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("iters", ctypes.c_int32), ("matvecs", ctypes.c_int32),
+                ("relres", ctypes.c_double)]
+
+
+class FidsError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} ({status})")
+
+
+_lib = None
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "fids_params_default": (ctypes.c_int, [ctypes.POINTER(Params)]),
+    "fids_workspace_size": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]),
+    "fids_init_problem": (ctypes.c_int, [ctypes.POINTER(Params), _P, _P, _P, _P, ctypes.c_size_t, _P,
+                                         ctypes.POINTER(_P)]),
+    "fids_step": (ctypes.c_int, [_P, _P, ctypes.POINTER(StepInfo)]),
+    "fids_solve_all": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(StepInfo)]),
+    "fids_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "fids_reset": (ctypes.c_int, [_P]),
+    "fids_destroy": (ctypes.c_int, [_P]),
+    "fids_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "fids_batch_workspace_size": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "fids_batch_init": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(_P),
+                                       ctypes.POINTER(_P), ctypes.POINTER(_P), _P, ctypes.c_size_t, _P,
+                                       ctypes.POINTER(_P)]),
+    "fids_batch_step": (ctypes.c_int, [_P, ctypes.POINTER(StepInfo)]),
+    "fids_batch_solve_all": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(StepInfo)]),
+    "fids_batch_reset": (ctypes.c_int, [_P]),
+    "fids_batch_destroy": (ctypes.c_int, [_P]),
+    "fids_soe_nodes": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int32, _D, _D, ctypes.POINTER(ctypes.c_int32)]),
+    "fids_ifl_column": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]),
+    "fids_strang_eigs": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]),
+    "fids_level_coefficients": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                               ctypes.c_double, _D]),
+}
+
+
+def lib():
+    """Load libfids.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2002_11978_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/fids.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(fids_\w+)\s*\(", txt, re.M)))
+
+
+def strerror(status: int) -> str:
+    try:
+        return lib().fids_strerror(status).decode()
+    except RuntimeError:
+        return f"status {status}"
+
+
+def _check(status, where):
+    if status != FIDS_OK:
+        raise FidsError(status, where)
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    _check(lib().fids_params_default(ctypes.byref(p)), "fids_params_default")
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def workspace_size(p: Params) -> int:
+    sz = ctypes.c_size_t(0)
+    _check(lib().fids_workspace_size(ctypes.byref(p), ctypes.byref(sz)), "fids_workspace_size")
+    return sz.value
+
+
+# ------------------------------------------------------------------ host-only helpers
+def _dptr(a):
+    return a.ctypes.data_as(_D)
+
+
+def soe_nodes(gamma, delta, T, tol, cap=4096):
+    import numpy as np
+    s = np.zeros(cap)
+    w = np.zeros(cap)
+    cnt = ctypes.c_int32(0)
+    _check(lib().fids_soe_nodes(gamma, delta, T, tol, cap, _dptr(s), _dptr(w), ctypes.byref(cnt)),
+           "fids_soe_nodes")
+    return s[: cnt.value].copy(), w[: cnt.value].copy()
+
+
+def ifl_column(n, alpha, l=1.0, mu=0.0):
+    import numpy as np
+    out = np.zeros(n)
+    _check(lib().fids_ifl_column(n, alpha, l, mu, _dptr(out)), "fids_ifl_column")
+    return out
+
+
+def strang_eigs(n, alpha, l=1.0, mu=0.0):
+    import numpy as np
+    out = np.zeros(n)
+    _check(lib().fids_strang_eigs(n, alpha, l, mu, _dptr(out)), "fids_strang_eigs")
+    return out
+
+
+def level_coefficients(gamma, T, M, r):
+    import numpy as np
+    out = np.zeros(M)
+    _check(lib().fids_level_coefficients(gamma, T, M, r, _dptr(out)), "fids_level_coefficients")
+    return out
+
+
+# ------------------------------------------------------------------ device problems
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+@dataclass
+class LevelReport:
+    m: int
+    iters: int
+    matvecs: int
+    relres: float
+
+
+class Problem:
+    """One problem of eq. (1.1) on the current CUDA (HIP) device.
+
+    kappa, f, phi are float64 device tensors in the layouts of fids.h; they
+    are borrowed (kept referenced here) for the lifetime of the handle.
+    """
+
+    def __init__(self, params: Params, kappa, f, phi, stream=None):
+        import torch
+        self.torch = torch
+        self.params = params
+        for name, t in (("kappa", kappa), ("f", f), ("phi", phi)):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 device tensor")
+        self.kappa, self.f, self.phi = kappa, f, phi
+        self.device = kappa.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ws_bytes = workspace_size(params)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p(0)
+        _check(lib().fids_init_problem(ctypes.byref(params), _ptr(kappa), _ptr(f), _ptr(phi), _ptr(self.ws),
+                                       self.ws_bytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                       ctypes.byref(h)), "fids_init_problem")
+        self.h = h
+
+    @property
+    def n(self):
+        return int(self.params.n)
+
+    @property
+    def M(self):
+        return int(self.params.M)
+
+    def step(self):
+        u = self.torch.empty(self.n, dtype=self.torch.float64, device=self.device)
+        info = StepInfo()
+        _check(lib().fids_step(self.h, _ptr(u), ctypes.byref(info)), "fids_step")
+        return u, LevelReport(info.m, info.iters, info.matvecs, info.relres)
+
+    def solve_all(self, return_all=False, want_uT=True):
+        torch = self.torch
+        uT = torch.empty(self.n, dtype=torch.float64, device=self.device) if want_uT else None
+        uall = torch.empty((self.M + 1, self.n), dtype=torch.float64, device=self.device) if return_all else None
+        infos = (StepInfo * self.M)()
+        st = lib().fids_solve_all(self.h, _ptr(uT), _ptr(uall), infos)
+        self.last_reports = [LevelReport(i.m, i.iters, i.matvecs, i.relres) for i in infos]
+        _check(st, "fids_solve_all")
+        return uT, uall, self.last_reports
+
+    def solve_all_raw(self, uT=None, uall=None, infos=None):
+        """Like solve_all with caller-provided outputs (no allocation)."""
+        return lib().fids_solve_all(self.h, _ptr(uT), _ptr(uall), infos)
+
+    def adjoint(self, dJ_duT, g_kappa=None, g_f=None, g_phi=None):
+        _check(lib().fids_adjoint(self.h, _ptr(dJ_duT), _ptr(g_kappa), _ptr(g_f), _ptr(g_phi)), "fids_adjoint")
+        return g_kappa, g_f, g_phi
+
+    def reset(self):
+        _check(lib().fids_reset(self.h), "fids_reset")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fids_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
