@@ -79,7 +79,11 @@ typedef struct fids_params {
     double  mu;           /* splitting parameter of (2.11), (alpha, 2]; 0 selects  */
                           /* 1 + alpha/2; kappa_mu = 2 when mu == 2 else 1         */
     double  soe_tol;      /* relative SOE tolerance on [tau_1, T] (Lemma 2.2)      */
-    double  krylov_tol;   /* stop when ||b - M x||_2 <= tol ||b||_2                */
+    double  krylov_tol;   /* stop when ||b - M x||_2 <= tol ||b||_2 (BiCGSTAB: its  */
+                          /* updated residual; FGMRES: the true FP64 residual, or  */
+                          /* that residual's attainable floor -- two restart       */
+                          /* cycles whose Arnoldi estimate met tol -- with the     */
+                          /* true value reported in fids_step_info.relres)         */
     int32_t krylov_maxit; /* max BiCGSTAB iterations / max FGMRES inner iterations */
                           /* summed over restarts, per time level                  */
     int32_t restart;      /* FGMRES Krylov dimension J (<= 32)                     */
@@ -144,8 +148,15 @@ int fids_solve_all(fids_problem* h, double* uT_d, double* u_all_d, fids_step_inf
 int fids_adjoint(fids_problem* h, const double* dJ_duT_d, double* g_kappa_d,
                  double* g_f_d, double* g_phi_d);
 
-/* Back to level 0 (u^0 = phi, empty history).  Tables are kept. */
+/* Back to level 0 (u^0 = phi, empty history).  Set-up tables are kept; the
+ * per-level preconditioner symbols are marked stale, so the next step or
+ * solve rebuilds them (every solve from level 0 includes that work). */
 int fids_reset(fids_problem* h);
+
+/* Builds the per-level Strang preconditioner symbols now (eq. 4.3 for every
+ * level: b_m' + kbar_m Lambda inverted through a length-n DFT and re-embedded
+ * in the length-L circulant) instead of inside the next step/solve. */
+int fids_prepare(fids_problem* h);
 
 /* Release the handle (not the caller's workspace or arrays).  NULL is a no-op. */
 int fids_destroy(fids_problem* h);

@@ -26,12 +26,16 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 int ilog2i(int64_t v) { int r = 0; while ((int64_t(1) << r) < v) ++r; return r; }
 
-// Shapes of a two-pass plan for Nc complex points.
+// Shapes of a two-pass plan for Nc complex points: Nc = N1 * N2, column tiles
+// of CT columns and row groups of RU row-pair units, each at most kTileCap
+// points so that a workgroup's ping-pong buffers fit in LDS.
 struct PlanShape {
-  int Nc, N1, N2, log1, log2, CT, ntiles, nunits;
+  int Nc, N1, N2, log1, log2, CT, ntiles, nunits, RU, nrg;
 };
 
-PlanShape plan_shape(int64_t Nc, int ct_override) {
+constexpr int kTileCap = 2048;
+
+PlanShape plan_shape(int64_t Nc, int target_tiles, int target_groups) {
   PlanShape s{};
   const int p = ilog2i(Nc);
   s.Nc = int(Nc);
@@ -39,13 +43,28 @@ PlanShape plan_shape(int64_t Nc, int ct_override) {
   s.log2 = p / 2;
   s.N1 = 1 << s.log1;
   s.N2 = 1 << s.log2;
-  int ct = ct_override > 0 ? ct_override : std::max(1, 2 * s.N2 / s.N1);
-  ct = std::min(ct, s.N2);
-  while (ct > 1 && ct * s.N1 > 1024) ct >>= 1;
+  int nt = 1;
+  while (nt * 2 <= std::min(target_tiles, s.N2)) nt *= 2;   // powers of two only
+  int ct = s.N2 / nt;
+  while (ct > 1 && ct * s.N1 > kTileCap) ct >>= 1;
   s.CT = ct;
   s.ntiles = s.N2 / s.CT;
   s.nunits = s.N1 / 2;
+  int ng = 1;
+  while (ng * 2 <= std::min(target_groups, s.nunits)) ng *= 2;
+  int ru = s.nunits / ng;
+  while (ru > 1 && 2 * ru * s.N2 > kTileCap) ru >>= 1;
+  s.RU = ru;
+  s.nrg = s.nunits / s.RU;
   return s;
+}
+
+// Workgroups per problem: about one per 2048 packed points (so a pass moves
+// about 32 KiB per workgroup), at most 32 -- the group barrier costs about
+// 1.5 us + 70 ns per workgroup on MI355X.
+int default_group(int64_t Nc) {
+  int64_t g = Nc / 2048;
+  return int(std::max<int64_t>(1, std::min<int64_t>(32, g)));
 }
 
 int env_int(const char* name, int dflt) {
@@ -60,7 +79,7 @@ struct Layout {
   size_t tw1r, tw1rf, tw2r, tw2rf, tw1c, tw1cf, tw2c, tw2cf, twlo, twlof, twhi, twhif;
   size_t qhat, qhatf;
   size_t Tb, q, Tq;
-  size_t u[3], F, kap, vec[10], uhist, T, Tf;
+  size_t u[3], F, kap, vec[10], uhist, T, Tf, tau, V, Z;
   size_t total;
   int chunk;
   int twshift;
@@ -69,7 +88,7 @@ struct Layout {
 struct Shapes {
   int64_t n, M, L, Nc;
   int nexp;
-  PlanShape pr, pc;
+  PlanShape pr, pc, ps;   // level plan, Bluestein (complex L) plan, symbol (real) plan
 };
 
 Layout make_layout(const fids_params& p, const Shapes& sh) {
@@ -85,6 +104,7 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   lo.info = take(M * sizeof(fids_step_info));
   lo.part = take(size_t(fids::SL_COUNT) * sh.pr.ntiles * sizeof(double));
   lo.beta = take((M + 1) * 8);
+  lo.tau = take((M + 1) * 8);
   lo.theta = take((M + 1) * ne * 8);
   lo.decay = take((M + 1) * ne * 8);
   lo.gw = take(ne * 8);
@@ -116,6 +136,9 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   lo.kap = take(L * 8);
   for (int i = 0; i < 10; ++i) lo.vec[i] = take(L * 8);
   lo.uhist = p.store_states ? take((M + 1) * L * 8) : 0;
+  const bool gm = p.solver == FIDS_FGMRES;
+  lo.V = gm ? take(size_t(p.restart + 1) * L * 8) : 0;
+  lo.Z = gm ? take(size_t(p.restart) * L * (mixed ? 4 : 8)) : 0;
   lo.T = take(Nc * 16);
   lo.Tf = take(Nc * 8);
   lo.total = off;
@@ -132,8 +155,14 @@ int shapes_of(const fids_params& p, Shapes& sh, fids::SoeNodes* soe_out) {
   const double tau1 = p.T * std::pow(1.0 / double(p.M), p.r);
   if (fids::soe_build(p.gamma, tau1, p.T, p.soe_tol, soe) != FIDS_OK) return FIDS_EINVAL;
   sh.nexp = int(soe.s.size());
-  sh.pr = plan_shape(sh.Nc, env_int("FIDS_CT", 0));
-  sh.pc = plan_shape(sh.L, 8);
+  const int grp = p.wg_count > 0 ? p.wg_count : env_int("FIDS_WG", default_group(sh.Nc));
+  sh.pr = plan_shape(sh.Nc, grp, grp);
+  sh.pc = plan_shape(sh.L, std::max(1, int((sh.L >> ((ilog2i(sh.L) + 1) / 2)) / 8)), 1 << 30);
+  sh.pc.RU = 1;
+  sh.pc.nrg = sh.pc.nunits;
+  sh.ps = plan_shape(sh.Nc, std::max(1, int((sh.Nc >> ((ilog2i(sh.Nc) + 1) / 2)) / 8)), 1 << 30);
+  sh.ps.RU = 1;
+  sh.ps.nrg = sh.ps.nunits;
   if (soe_out) *soe_out = soe;
   return FIDS_OK;
 }
@@ -206,7 +235,7 @@ int upload(fids_problem* h, size_t off, const void* src, size_t bytes) {
 
 void fill_plan(Plan& pl, const PlanShape& s, int rootmul, char* ws, const Layout& lo, bool complex_plan) {
   pl.Nc = s.Nc; pl.N1 = s.N1; pl.N2 = s.N2; pl.log1 = s.log1; pl.log2 = s.log2; pl.CT = s.CT;
-  pl.ntiles = s.ntiles; pl.nunits = s.nunits; pl.rootmul = rootmul;
+  pl.ntiles = s.ntiles; pl.nunits = s.nunits; pl.RU = s.RU; pl.nrg = s.nrg; pl.rootmul = rootmul;
   pl.twshift = lo.twshift; pl.twmask = (1 << lo.twshift) - 1;
   pl.tw1 = at<double2>(ws, complex_plan ? lo.tw1c : lo.tw1r);
   pl.tw1f = at<float2>(ws, complex_plan ? lo.tw1cf : lo.tw1rf);
@@ -285,7 +314,6 @@ const char* fids_strerror(int s) {
 
 int fids_workspace_size(const fids_params* p, size_t* bytes) {
   if (!p || !bytes) return FIDS_EINVAL;
-  if (p->solver != FIDS_BICGSTAB) return FIDS_EINVAL;  // FGMRES path is built separately
   Shapes sh;
   if (shapes_of(*p, sh, nullptr) != FIDS_OK) return FIDS_EINVAL;
   *bytes = make_layout(*p, sh).total;
@@ -295,7 +323,6 @@ int fids_workspace_size(const fids_params* p, size_t* bytes) {
 int fids_init_problem(const fids_params* p, const double* kappa_d, const double* f_d, const double* phi_d,
                       void* ws_d, size_t ws_bytes, void* hip_stream, fids_problem** out) {
   if (!p || !kappa_d || !f_d || !phi_d || !ws_d || !out) return FIDS_EINVAL;
-  if (p->solver != FIDS_BICGSTAB) return FIDS_EINVAL;
   if (reinterpret_cast<uintptr_t>(ws_d) % kAlign) return FIDS_EINVAL;
   *out = nullptr;
   fids_problem* h = new (std::nothrow) fids_problem();
@@ -318,6 +345,7 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
   if (hipMemsetAsync(ws, 0, lo.total, h->stream) != hipSuccess) return fail(FIDS_EDEVICE);
   // tables
   st |= upload(h, lo.beta, t.beta.data(), t.beta.size() * 8);
+  st |= upload(h, lo.tau, t.tau.data(), t.tau.size() * 8);
   st |= upload(h, lo.theta, t.theta.data(), t.theta.size() * 8);
   st |= upload(h, lo.decay, t.decay.data(), t.decay.size() * 8);
   st |= upload(h, lo.gw, t.gw.data(), t.gw.size() * 8);
@@ -346,11 +374,9 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
   hp.restart = p->restart; hp.store_states = p->store_states; hp.tol = p->krylov_tol;
   hp.L = int(h->sh.L); hp.vlen = int(h->sh.L);
   fill_plan(hp.pl, h->sh.pr, 2, ws, lo, false);
-  const int maxg = std::max(hp.pl.ntiles, hp.pl.nunits);
-  int ng = p->wg_count > 0 ? p->wg_count : env_int("FIDS_WG", std::min(maxg, 256));
-  ng = std::max(1, std::min(ng, maxg));
-  hp.g0 = 0; hp.ng = ng;
-  hp.beta = at<double>(ws, lo.beta); hp.theta = at<double>(ws, lo.theta); hp.decay = at<double>(ws, lo.decay);
+  hp.g0 = 0;
+  hp.ng = std::max(hp.pl.ntiles, hp.pl.nrg);
+  hp.beta = at<double>(ws, lo.beta); hp.tau = at<double>(ws, lo.tau); hp.theta = at<double>(ws, lo.theta); hp.decay = at<double>(ws, lo.decay);
   hp.gw = at<double>(ws, lo.gw); hp.ahat = at<double>(ws, lo.ahat);
   hp.qhat = lo.qhat ? at<double>(ws, lo.qhat) : nullptr;
   hp.qhatf = lo.qhatf ? at<float>(ws, lo.qhatf) : nullptr;
@@ -358,7 +384,10 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
   for (int i = 0; i < 3; ++i) hp.u[i] = at<double>(ws, lo.u[i]);
   hp.F = at<double>(ws, lo.F); hp.kap = at<double>(ws, lo.kap);
   for (int i = 0; i < 10; ++i) hp.vec[i] = at<double>(ws, lo.vec[i]);
-  hp.zf = nullptr; hp.V = nullptr;
+  const bool mixed = p->precision == FIDS_MIXED;
+  hp.V = lo.V ? at<double>(ws, lo.V) : nullptr;
+  hp.zd = (lo.Z && !mixed) ? at<double>(ws, lo.Z) : nullptr;
+  hp.zf = (lo.Z && mixed) ? at<float>(ws, lo.Z) : nullptr;
   hp.uhist = lo.uhist ? at<double>(ws, lo.uhist) : nullptr;
   hp.T = at<double2>(ws, lo.T); hp.Tf = at<float2>(ws, lo.Tf);
   hp.part = at<double>(ws, lo.part);
@@ -372,7 +401,7 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
   SymJob& j = h->hj;
   j.n = int(p->n); j.L = int(h->sh.L); j.Nc = int(h->sh.Nc); j.M = int(p->M);
   fill_plan(j.plc, h->sh.pc, 1, ws, lo, true);
-  fill_plan(j.plr, h->sh.pr, 2, ws, lo, false);
+  fill_plan(j.plr, h->sh.ps, 2, ws, lo, false);
   j.beta = hp.beta; j.kbar = at<double>(ws, lo.kbar); j.lam = at<double>(ws, lo.lam);
   j.chirp = at<double2>(ws, lo.chirp); j.chirp_hat = at<double2>(ws, lo.chirp_hat);
   j.Tb = at<double2>(ws, lo.Tb); j.q = at<double>(ws, lo.q); j.Tq = at<double2>(ws, lo.Tq);
@@ -382,6 +411,7 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
   if (upload(h, lo.prob, &h->hp, sizeof(Prob)) != FIDS_OK) return fail(FIDS_EDEVICE);
   if (upload(h, lo.job, &h->hj, sizeof(SymJob)) != FIDS_OK) return fail(FIDS_EDEVICE);
   h->lds = fids::level_lds_bytes(hp);
+  if (h->lds > 65536 && fids::set_level_lds_limit(h->lds) != hipSuccess) return fail(FIDS_EDEVICE);
   if (fids::launch_init_state(hp, h->dp, h->stream) != hipSuccess) return fail(FIDS_EDEVICE);
   int dev = 0, rate_khz = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(FIDS_EDEVICE);
@@ -399,6 +429,14 @@ int fids_reset(fids_problem* h) {
   HIPCHK(hipStreamSynchronize(h->stream));
   h->level = 0;
   h->symbols_ready = false;  // every solve from level 0 rebuilds the per-level symbols
+  return FIDS_OK;
+}
+
+int fids_prepare(fids_problem* h) {
+  if (!h) return FIDS_EINVAL;
+  const int st = ensure_symbols(h);
+  if (st != FIDS_OK) return st;
+  HIPCHK(hipStreamSynchronize(h->stream));
   return FIDS_OK;
 }
 

@@ -14,7 +14,7 @@
 
 namespace fids {
 
-constexpr int kThreads = 256;     // threads per workgroup in every kernel
+constexpr int kThreads = 512;     // threads per workgroup in every kernel
 constexpr int kMaxFFT = 4096;     // longest per-workgroup FFT (complex points)
 constexpr int kMaxRestart = 32;
 
@@ -30,6 +30,8 @@ struct Plan {
   int Nc, N1, N2, log1, log2, CT;
   int ntiles;        // N2 / CT column tiles
   int nunits;        // N1 / 2 row-pair units
+  int RU;            // row-pair units per row group
+  int nrg;           // nunits / RU row groups
   int rootmul;       // W_Nc = W_root^rootmul (2 for the real-packed plan, 1 complex)
   int twshift;       // split of the root table: j = (jh << twshift) + jl
   int twmask;
@@ -49,6 +51,7 @@ struct Prob {
   Plan pl;                      // real-packed plan, Nc = L/2
   // set-up tables
   const double* beta;           // [M+1]
+  const double* tau;            // [M+1] tau_m = t_m - t_{m-1}
   const double* theta;          // [(M+1) * nexp]
   const double* decay;          // [(M+1) * nexp]
   const double* gw;             // [nexp]
@@ -64,7 +67,8 @@ struct Prob {
   double* F;                    // [ntiles][nexp][2*CT*N1]
   double* kap;                  // kappa^m, tile-major
   double* vec[10];              // Krylov vectors (solver specific)
-  float* zf;                    // FGMRES: Z basis in FP32, [restart][vlen]
+  float* zf;                    // FGMRES: Z basis in FP32 (mixed), [restart][vlen]
+  double* zd;                   // FGMRES: Z basis in FP64, [restart][vlen]
   double* V;                    // FGMRES: V basis, [restart+1][vlen]
   double* uhist;                // [(M+1)][vlen] when store_states
   double2* T;                   // FFT intermediate, Nc complex

@@ -124,9 +124,9 @@ __device__ __forceinline__ Cx<R>* lds_fft(Cx<R>* src, Cx<R>* dst, int P, int log
 template <typename R>
 __device__ __forceinline__ void tileA_fft_store(const Plan& pl, int tile, Cx<R>* buf, Cx<R>* T) {
   __syncthreads();
-  const Cx<R>* res = lds_fft<R>(buf, buf + pl.CT * pl.N1, pl.N1, pl.log1, pl.CT, -1, tw_n1<R>(pl));
-  const int c0 = tile * pl.CT, logCT = ilog2(pl.CT);
   const int total = pl.CT * pl.N1;
+  const Cx<R>* res = lds_fft<R>(buf, buf + total, pl.N1, pl.log1, pl.CT, -1, tw_n1<R>(pl));
+  const int c0 = tile * pl.CT, logCT = ilog2(pl.CT);
   for (int idx = threadIdx.x; idx < total; idx += kThreads) {
     const int c = idx & (pl.CT - 1), k1 = idx >> logCT;
     Cx<R> v = res[c * pl.N1 + k1];
@@ -137,8 +137,7 @@ __device__ __forceinline__ void tileA_fft_store(const Plan& pl, int tile, Cx<R>*
 }
 
 // Column pass C: load T[k1*N2 + n2] for the tile, inverse N1-point FFTs;
-// afterwards buf[c*N1 + n1] = Nc * z'[N2*n1 + c0 + c] (the result is copied
-// back into the first half of buf when the stage count is odd).
+// afterwards buf[c*N1 + n1] = Nc * z'[N2*n1 + c0 + c].
 template <typename R>
 __device__ __forceinline__ void tileC_load_ifft(const Plan& pl, int tile, const Cx<R>* T, Cx<R>* buf) {
   const int c0 = tile * pl.CT, logCT = ilog2(pl.CT);
@@ -156,39 +155,48 @@ __device__ __forceinline__ void tileC_load_ifft(const Plan& pl, int tile, const 
   }
 }
 
-// Row pass B of a real-packed transform, one unit = rows (u, N1-u), or rows
-// (0, N1/2) for u = 0.  Forward N2-point FFTs give Z[k1 + N1 k2]; each Z[k]
-// is paired with Z[Nc-k] to split the spectrum X of the real length-L input,
+// row k1 of side s (0 or 1) of row-pair unit u: (u, N1-u), and (0, N1/2) for u = 0.
+__device__ __forceinline__ int unit_row(const Plan& pl, int u, int side) {
+  return side == 0 ? u : (u == 0 ? (pl.N1 >> 1) : pl.N1 - u);
+}
+
+// Row pass B of a real-packed transform over row group `grp` (RU units, 2 RU
+// rows).  Forward N2-point FFTs give Z[k1 + N1 k2]; each Z[k] is paired with
+// Z[Nc-k] (the other row of its unit) to split the spectrum X of the real
+// length-L input,
 //   X[k] = E + W_L^k O,  X[k+Nc] = E - W_L^k O,
 //   E = (Z[k] + Z*[Nc-k])/2,  O = -i (Z[k] - Z*[Nc-k])/2.
 // mode 0: multiply by the real even symbol S (S[k], S[Nc-k]), repack for the
 // inverse, inverse N2-point FFTs, twiddle W_Nc^{-n2 k1}, store T.
 // mode 1: write Re X[k] (k < Nc) and Re X[Nc] to spec / specf.
+// buf has room for 4 RU N2 points.
 template <typename R, typename RS>
-__device__ __forceinline__ void rowB_real(const Plan& pl, int unit, const Cx<R>* Tin, Cx<R>* Tout, const RS* S,
-                          Cx<R>* buf, int mode, double* spec, float* specf) {
+__device__ __forceinline__ void rowB_real(const Plan& pl, int grp, const Cx<R>* Tin, Cx<R>* Tout, const RS* S,
+                                          Cx<R>* buf, int mode, double* spec, float* specf) {
   const int N1 = pl.N1, N2 = pl.N2, Nc = pl.Nc;
-  const int ka = unit, kb = (unit == 0) ? (N1 >> 1) : (N1 - unit);
+  const int nrow = 2 * pl.RU, u0 = grp * pl.RU;
+  const int tot = nrow * N2;
   Cx<R>* b0 = buf;
-  Cx<R>* b1 = buf + 2 * N2;
+  Cx<R>* b1 = buf + tot;
   __syncthreads();
-  for (int idx = threadIdx.x; idx < 2 * N2; idx += kThreads) {
-    const int r = idx >> pl.log2, n2 = idx & (N2 - 1);
-    b0[idx] = Tin[(r ? kb : ka) * N2 + n2];
+  for (int idx = threadIdx.x; idx < tot; idx += kThreads) {
+    const int q = idx >> pl.log2, n2 = idx & (N2 - 1);
+    b0[idx] = Tin[unit_row(pl, u0 + (q >> 1), q & 1) * N2 + n2];
   }
   __syncthreads();
   {
-    Cx<R>* res = lds_fft<R>(b0, b1, N2, pl.log2, 2, -1, tw_n2<R>(pl));
+    Cx<R>* res = lds_fft<R>(b0, b1, N2, pl.log2, nrow, -1, tw_n2<R>(pl));
     if (res != b0) { b1 = b0; b0 = res; }   // b0: spectrum rows, b1: free
   }
-  for (int idx = threadIdx.x; idx < 2 * N2; idx += kThreads) {
-    const int r = idx >> pl.log2, k2 = idx & (N2 - 1);
-    const int k1 = r ? kb : ka;
+  for (int idx = threadIdx.x; idx < tot; idx += kThreads) {
+    const int q = idx >> pl.log2, k2 = idx & (N2 - 1);
+    const int u = u0 + (q >> 1);
+    const int k1 = unit_row(pl, u, q & 1);
     const int k = k1 + N1 * k2;
-    const int pr = (unit == 0) ? r : 1 - r;
+    const int pq = (u == 0) ? q : (q ^ 1);
     const int pk2 = (k1 == 0) ? ((N2 - k2) & (N2 - 1)) : (N2 - 1 - k2);
     const Cx<R> Zk = b0[idx];
-    const Cx<R> Zt = cconj<R>(b0[pr * N2 + pk2]);
+    const Cx<R> Zt = cconj<R>(b0[pq * N2 + pk2]);
     const Cx<R> E = cscale<R>(cadd<R>(Zk, Zt), R(0.5));
     const Cx<R> D = csub<R>(Zk, Zt);
     const Cx<R> O = mk<R>(R(0.5) * D.y, R(-0.5) * D.x);
@@ -212,10 +220,10 @@ __device__ __forceinline__ void rowB_real(const Plan& pl, int unit, const Cx<R>*
   }
   if (mode != 0) return;
   __syncthreads();
-  const Cx<R>* res = lds_fft<R>(b1, b0, N2, pl.log2, 2, +1, tw_n2<R>(pl));
-  for (int idx = threadIdx.x; idx < 2 * N2; idx += kThreads) {
-    const int r = idx >> pl.log2, n2 = idx & (N2 - 1);
-    const int k1 = r ? kb : ka;
+  const Cx<R>* res = lds_fft<R>(b1, b0, N2, pl.log2, nrow, +1, tw_n2<R>(pl));
+  for (int idx = threadIdx.x; idx < tot; idx += kThreads) {
+    const int q = idx >> pl.log2, n2 = idx & (N2 - 1);
+    const int k1 = unit_row(pl, u0 + (q >> 1), q & 1);
     Cx<R> v = res[idx];
     const unsigned e = unsigned(n2 * k1) * unsigned(pl.rootmul);
     if (e) v = cmulc<R>(v, tw_root<R>(pl, e));
@@ -223,29 +231,31 @@ __device__ __forceinline__ void rowB_real(const Plan& pl, int unit, const Cx<R>*
   }
 }
 
-// Row pass B of a complex transform: forward N2-point FFTs, multiply by the
-// complex symbol Sc[k1 + N1 k2], inverse, twiddle, store.
-__device__ __forceinline__ void rowB_complex(const Plan& pl, int unit, double2* T, const double2* Sc, double2* buf) {
+// Row pass B of a complex transform (row group of RU units): forward N2-point
+// FFTs, multiply by the complex symbol Sc[k1 + N1 k2], inverse, twiddle, store.
+__device__ __forceinline__ void rowB_complex(const Plan& pl, int grp, double2* T, const double2* Sc,
+                                             double2* buf) {
   const int N1 = pl.N1, N2 = pl.N2;
-  const int ka = unit, kb = (unit == 0) ? (N1 >> 1) : (N1 - unit);
+  const int nrow = 2 * pl.RU, u0 = grp * pl.RU;
+  const int tot = nrow * N2;
   __syncthreads();
-  for (int idx = threadIdx.x; idx < 2 * N2; idx += kThreads) {
-    const int r = idx >> pl.log2, n2 = idx & (N2 - 1);
-    buf[idx] = T[(r ? kb : ka) * N2 + n2];
+  for (int idx = threadIdx.x; idx < tot; idx += kThreads) {
+    const int q = idx >> pl.log2, n2 = idx & (N2 - 1);
+    buf[idx] = T[unit_row(pl, u0 + (q >> 1), q & 1) * N2 + n2];
   }
   __syncthreads();
-  double2* res = lds_fft<double>(buf, buf + 2 * N2, N2, pl.log2, 2, -1, pl.tw2);
-  double2* oth = (res == buf) ? buf + 2 * N2 : buf;
-  for (int idx = threadIdx.x; idx < 2 * N2; idx += kThreads) {
-    const int r = idx >> pl.log2, k2 = idx & (N2 - 1);
-    const int k1 = r ? kb : ka;
+  double2* res = lds_fft<double>(buf, buf + tot, N2, pl.log2, nrow, -1, pl.tw2);
+  double2* oth = (res == buf) ? buf + tot : buf;
+  for (int idx = threadIdx.x; idx < tot; idx += kThreads) {
+    const int q = idx >> pl.log2, k2 = idx & (N2 - 1);
+    const int k1 = unit_row(pl, u0 + (q >> 1), q & 1);
     res[idx] = cmul<double>(res[idx], Sc[k1 + N1 * k2]);
   }
   __syncthreads();
-  res = lds_fft<double>(res, oth, N2, pl.log2, 2, +1, pl.tw2);
-  for (int idx = threadIdx.x; idx < 2 * N2; idx += kThreads) {
-    const int r = idx >> pl.log2, n2 = idx & (N2 - 1);
-    const int k1 = r ? kb : ka;
+  res = lds_fft<double>(res, oth, N2, pl.log2, nrow, +1, pl.tw2);
+  for (int idx = threadIdx.x; idx < tot; idx += kThreads) {
+    const int q = idx >> pl.log2, n2 = idx & (N2 - 1);
+    const int k1 = unit_row(pl, u0 + (q >> 1), q & 1);
     double2 v = res[idx];
     const unsigned e = unsigned(n2 * k1) * unsigned(pl.rootmul);
     if (e) v = cmulc<double>(v, tw_root<double>(pl, e));
@@ -296,6 +306,27 @@ __device__ __forceinline__ void reduce_slots(const Prob& p, const int (&slot)[NV
   block_sum<NV>(out);
 }
 
+// Reduce `cnt` consecutive slots starting at `s0` into out[0..cnt) (LDS).
+__device__ __forceinline__ void reduce_range(const Prob& p, int s0, int cnt, double* out) {
+  const int nt = p.pl.ntiles;
+  for (int b = 0; b < cnt; b += 8) {
+    double v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      double s = 0;
+      if (b + i < cnt)
+        for (int t = threadIdx.x; t < nt; t += kThreads) s += p.part[(s0 + b + i) * nt + t];
+      v[i] = s;
+    }
+    block_sum<8>(v);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (b + i < cnt) out[b + i] = v[i];
+  }
+  __syncthreads();
+}
+
 template <int NV>
 __device__ __forceinline__ void write_partials(const Prob& p, int tile, const int (&slot)[NV], double (&v)[NV]) {
   block_sum<NV>(v);
@@ -311,7 +342,7 @@ __device__ __forceinline__ void write_partials(const Prob& p, int tile, const in
 // abort raised by another workgroup makes every waiter return false, so the
 // launch always drains.
 __device__ __forceinline__ bool group_barrier(const Prob& p, unsigned& gen, unsigned long long timeout,
-                              int* abort_flag) {
+                                              int* abort_flag) {
   __shared__ int s_ok;
   __syncthreads();
   if (p.ng == 1) return true;
@@ -372,16 +403,64 @@ __device__ __forceinline__ double2 nat2(const double* a, int i0, int n) {
 __device__ __forceinline__ double2 mask2(double2 v, int i0, int n) {
   return make_double2(i0 < n ? v.x : 0.0, i0 + 1 < n ? v.y : 0.0);
 }
+template <typename R> __device__ __forceinline__ Cx<R> tocx(double2 v) { return mk<R>(R(v.x), R(v.y)); }
+template <typename R> __device__ __forceinline__ double2 fromcx(Cx<R> v) { return make_double2(double(v.x), double(v.y)); }
 
-// ------------------------------------------------------------- BiCGSTAB level
-// Vector roles in Prob::vec for BiCGSTAB.
-enum { VR = 0, VRH, VP, VV, VS, VT, VPH, VSH };
+// views of the problem in the preconditioner precision R
+template <typename R> __device__ __forceinline__ Cx<R>* pT(const Prob& p);
+template <> __device__ __forceinline__ double2* pT<double>(const Prob& p) { return p.T; }
+template <> __device__ __forceinline__ float2* pT<float>(const Prob& p) { return p.Tf; }
+template <typename R> __device__ __forceinline__ const R* pQ(const Prob& p, int m);
+template <> __device__ __forceinline__ const double* pQ<double>(const Prob& p, int m) {
+  return p.qhat + size_t(m) * (p.pl.Nc + 1);
+}
+template <> __device__ __forceinline__ const float* pQ<float>(const Prob& p, int m) {
+  return p.qhatf + size_t(m) * (p.pl.Nc + 1);
+}
+// FGMRES Z basis, stored in the preconditioner precision
+template <typename R> __device__ __forceinline__ double2 z_get(const Prob& p, int i, int off);
+template <> __device__ __forceinline__ double2 z_get<double>(const Prob& p, int i, int off) {
+  return ld2(p.zd + size_t(i) * p.vlen, off);
+}
+template <> __device__ __forceinline__ double2 z_get<float>(const Prob& p, int i, int off) {
+  const float2 v = *reinterpret_cast<const float2*>(p.zf + size_t(i) * p.vlen + off);
+  return make_double2(double(v.x), double(v.y));
+}
+// store z and return the stored (rounded) value
+template <typename R> __device__ __forceinline__ double2 z_put(const Prob& p, int i, int off, double2 v);
+template <> __device__ __forceinline__ double2 z_put<double>(const Prob& p, int i, int off, double2 v) {
+  st2(p.zd + size_t(i) * p.vlen, off, v);
+  return v;
+}
+template <> __device__ __forceinline__ double2 z_put<float>(const Prob& p, int i, int off, double2 v) {
+  const float2 f = make_float2(float(v.x), float(v.y));
+  *reinterpret_cast<float2*>(p.zf + size_t(i) * p.vlen + off) = f;
+  return make_double2(double(f.x), double(f.y));
+}
+
+// ------------------------------------------------------------- level state
+// Vector roles in Prob::vec (VV doubles as the FGMRES vector w).
+enum { VB = 0, VR, VRH, VP, VV, VS, VT, VPH, VSH };
 
 struct Ctl {
   unsigned gen;
   unsigned long long timeout;
   int* abort_flag;
 };
+
+// FGMRES small state in LDS: hraw (J+1)J, R J*J, and 8 vectors of J+1.
+constexpr int kSmallDoubles = ((kMaxRestart + 1) * kMaxRestart + kMaxRestart * kMaxRestart + 8 * (kMaxRestart + 1) + 1) / 2 * 2;
+
+// LDS carve-up of the level kernel.
+struct Lds {
+  double* tab;      // 3 * nexp SOE factors
+  double* small;    // FGMRES Hessenberg state
+  double2* bd;      // FP64 tile / row buffer
+  float2* bf;       // FP32 tile / row buffer
+};
+template <typename R> __device__ __forceinline__ Cx<R>* lbuf(const Lds& L);
+template <> __device__ __forceinline__ double2* lbuf<double>(const Lds& L) { return L.bd; }
+template <> __device__ __forceinline__ float2* lbuf<float>(const Lds& L) { return L.bf; }
 
 #define BARRIER()                                                     \
   do {                                                                \
@@ -390,7 +469,8 @@ struct Ctl {
     }                                                                 \
   } while (0)
 
-__device__ __forceinline__ void write_info(const Prob& p, int rank, int m, int iters, int matvecs, double relres, int status) {
+__device__ __forceinline__ void write_info(const Prob& p, int rank, int m, int iters, int matvecs, double relres,
+                                           int status) {
   if (rank == 0 && threadIdx.x == 0) {
     fids_step_info in;
     in.m = m;
@@ -403,15 +483,23 @@ __device__ __forceinline__ void write_info(const Prob& p, int rank, int m, int i
   }
 }
 
-// SOE history update + right-hand side for level m, fused with the first
-// column pass of P_m^{-1} applied to b (x0 = 0 so r = r^ = p = b).
-__device__ __forceinline__ void phase_soe(const Prob& p, int m, int rank, double* lds_tab, double2* buf) {
+__device__ __forceinline__ bool bad(double v) { return !isfinite(v); }
+
+// ------------------------------------------------------------- phases
+// Right-hand side of level m: SOE history update (in place) and
+// b = b_m' u^{m-1} - sum_j g w_j F_j + f^m; kappa^m copied tile-major.
+// Initial guess x0 = 0, or the linear extrapolation
+// u^{m-1} + (tau_m / tau_{m-1}) (u^{m-1} - u^{m-2}) (x0_mode 1).
+// Writes b (VB), x0 (u^m slot), partial (b,b); then either the column pass
+// of P^{-1} on r0 = b (x0 = 0; for BiCGSTAB also r^ = p = b) or the column
+// pass of A on x0.
+template <typename RP>
+__device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const Lds& L) {
   const Plan& pl = p.pl;
   const int nexp = p.nexp;
-  // per-level SOE factors into LDS (shared by all tiles of this workgroup)
-  double* th = lds_tab;
-  double* de = lds_tab + nexp;
-  double* gw = lds_tab + 2 * nexp;
+  double* th = L.tab;
+  double* de = L.tab + nexp;
+  double* gw = L.tab + 2 * nexp;
   __syncthreads();
   for (int j = threadIdx.x; j < nexp; j += kThreads) {
     th[j] = p.theta[size_t(m) * nexp + j];
@@ -420,6 +508,9 @@ __device__ __forceinline__ void phase_soe(const Prob& p, int m, int rank, double
   }
   __syncthreads();
   const double bm = p.beta[m];
+  const double rho = (m >= 2) ? p.tau[m] / p.tau[m - 1] : 0.0;
+  const bool warm = p.x0_mode != 0;
+  const bool bicg = p.solver == FIDS_BICGSTAB;
   const double* um1 = p.u[(m - 1) % 3];
   const double* um2 = p.u[(m + 1) % 3];  // (m-2) mod 3
   double* x = p.u[m % 3];
@@ -433,13 +524,14 @@ __device__ __forceinline__ void phase_soe(const Prob& p, int m, int rank, double
       int i0, sl;
       item(pl, t, idx, i0, sl);
       const int off = t.toff + 2 * idx;
-      double2 b = make_double2(0.0, 0.0);
+      double2 b = make_double2(0.0, 0.0), x0 = make_double2(0.0, 0.0);
       if (i0 < p.n) {
         const double2 a1 = ld2(um1, off);
         double2 h = make_double2(0.0, 0.0);
+        double2 d = make_double2(0.0, 0.0);
         if (m >= 2) {
           const double2 a2 = ld2(um2, off);
-          const double2 d = make_double2(a1.x - a2.x, a1.y - a2.y);
+          d = make_double2(a1.x - a2.x, a1.y - a2.y);
           double* Fp = p.F + size_t(tile) * nexp * blk + 2 * idx;
           for (int j = 0; j < nexp; ++j) {
             double2 fj = ld2(Fp, j * blk);
@@ -452,49 +544,90 @@ __device__ __forceinline__ void phase_soe(const Prob& p, int m, int rank, double
         }
         const double2 fv = nat2(fm, i0, p.n);
         b = mask2(make_double2(bm * a1.x - h.x + fv.x, bm * a1.y - h.y + fv.y), i0, p.n);
+        if (warm) x0 = mask2(make_double2(a1.x + rho * d.x, a1.y + rho * d.y), i0, p.n);
         st2(p.kap, off, nat2(km, i0, p.n));
         if (p.store_states) st2(p.uhist + size_t(m - 1) * p.vlen, off, a1);
       }
-      st2(p.vec[VR], off, b);
-      st2(p.vec[VRH], off, b);
-      st2(p.vec[VP], off, b);
-      st2(x, off, make_double2(0.0, 0.0));
+      st2(p.vec[VB], off, b);
+      st2(x, off, x0);
+      if (!warm) {
+        st2(p.vec[VR], off, b);
+        if (bicg) { st2(p.vec[VRH], off, b); st2(p.vec[VP], off, b); }
+      }
       acc[0] += b.x * b.x + b.y * b.y;
-      buf[sl] = b;
+      if (warm) L.bd[sl] = x0;
+      else lbuf<RP>(L)[sl] = tocx<RP>(b);
     }
     const int sl_bb[1] = {SL_BB};
     write_partials<1>(p, tile, sl_bb, acc);
-    tileA_fft_store<double>(pl, tile, buf, p.T);
+    if (warm) tileA_fft_store<double>(pl, tile, L.bd, p.T);
+    else tileA_fft_store<RP>(pl, tile, lbuf<RP>(L), pT<RP>(p));
   }
 }
 
-// B pass with symbol S over all units of the problem.
-template <typename RS>
-__device__ __forceinline__ void phase_rows(const Prob& p, int rank, const RS* S, double2* buf) {
-  for (int u = rank; u < p.pl.nunits; u += p.ng) rowB_real<double, RS>(p.pl, u, p.T, p.T, S, buf, 0, nullptr, nullptr);
+// Row pass of a symbol over all row groups of the problem.
+template <typename R, typename RS>
+__device__ __forceinline__ void phase_rows(const Prob& p, int rank, const RS* S, Cx<R>* T, Cx<R>* buf) {
+  for (int g = rank; g < p.pl.nrg; g += p.ng) rowB_real<R, RS>(p.pl, g, T, T, S, buf, 0, nullptr, nullptr);
 }
 
+// Residual r = b - (b_m' x + kappa .* A x) after the row pass of A on x;
+// stores r (and r^ = p = r for BiCGSTAB), partial (r, r), then the column
+// pass of P^{-1} on r.
+template <typename RP>
+__device__ __forceinline__ void phase_r0(const Prob& p, int m, int rank, const Lds& L) {
+  const Plan& pl = p.pl;
+  const double inv = 1.0 / double(pl.Nc);
+  const double bm = p.beta[m];
+  const double* x = p.u[m % 3];
+  const bool bicg = p.solver == FIDS_BICGSTAB;
+  for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
+    const TileIdx t = tile_idx(pl, tile);
+    tileC_load_ifft<double>(pl, tile, p.T, L.bd);
+    double acc[1] = {0.0};
+    for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
+      int i0, sl;
+      item(pl, t, idx, i0, sl);
+      const int off = t.toff + 2 * idx;
+      double2 r = make_double2(0.0, 0.0);
+      if (i0 < p.n) {
+        const double2 y = cscale<double>(L.bd[sl], inv);
+        const double2 xx = ld2(x, off), kk = ld2(p.kap, off), b = ld2(p.vec[VB], off);
+        r = mask2(make_double2(b.x - (bm * xx.x + kk.x * y.x), b.y - (bm * xx.y + kk.y * y.y)), i0, p.n);
+      }
+      st2(p.vec[VR], off, r);
+      if (bicg) { st2(p.vec[VRH], off, r); st2(p.vec[VP], off, r); }
+      acc[0] += r.x * r.x + r.y * r.y;
+      lbuf<RP>(L)[sl] = tocx<RP>(r);
+    }
+    const int sl_rr[1] = {SL_RR};
+    write_partials<1>(p, tile, sl_rr, acc);
+    tileA_fft_store<RP>(pl, tile, lbuf<RP>(L), pT<RP>(p));
+  }
+}
+
+// ------------------------------------------------------------- BiCGSTAB
 // C pass of P^{-1}: z = crop(IFFT), store z into vec[dst], then A pass of A on z.
-__device__ __forceinline__ void phase_C_then_A(const Prob& p, int rank, int dst, double2* buf) {
+__device__ __forceinline__ void bi_C_then_A(const Prob& p, int rank, int dst, const Lds& L) {
   const Plan& pl = p.pl;
   const double inv = 1.0 / double(pl.Nc);
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
-    tileC_load_ifft<double>(pl, tile, p.T, buf);
+    tileC_load_ifft<double>(pl, tile, p.T, L.bd);
     for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
       int i0, sl;
       item(pl, t, idx, i0, sl);
-      const double2 z = mask2(cscale<double>(buf[sl], inv), i0, p.n);
+      const double2 z = mask2(cscale<double>(L.bd[sl], inv), i0, p.n);
       st2(p.vec[dst], t.toff + 2 * idx, z);
-      buf[sl] = z;
+      L.bd[sl] = z;
     }
-    tileA_fft_store<double>(pl, tile, buf, p.T);
+    tileA_fft_store<double>(pl, tile, L.bd, p.T);
   }
 }
 
 // C pass of A: y = A z;  out = b_m' z + kappa .* y;  partials of dots.
 // which = 0: v = M p^, partial (r^, v).   which = 1: t = M s^, partials (t,s), (t,t), (r^,t).
-__device__ __forceinline__ void phase_C_matvec(const Prob& p, int m, int rank, int which, double2* buf) {
+__device__ __forceinline__ void bi_C_matvec(const Prob& p, int m, int rank, int which, const Lds& L) {
   const Plan& pl = p.pl;
   const double inv = 1.0 / double(pl.Nc);
   const double bm = p.beta[m];
@@ -502,14 +635,14 @@ __device__ __forceinline__ void phase_C_matvec(const Prob& p, int m, int rank, i
   double* out = p.vec[which == 0 ? VV : VT];
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
-    tileC_load_ifft<double>(pl, tile, p.T, buf);
+    tileC_load_ifft<double>(pl, tile, p.T, L.bd);
     double acc[3] = {0.0, 0.0, 0.0};
     for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
       int i0, sl;
       item(pl, t, idx, i0, sl);
       if (i0 >= p.n) continue;
       const int off = t.toff + 2 * idx;
-      const double2 y = cscale<double>(buf[sl], inv);
+      const double2 y = cscale<double>(L.bd[sl], inv);
       const double2 zz = ld2(z, off), kk = ld2(p.kap, off);
       const double2 o = mask2(make_double2(bm * zz.x + kk.x * y.x, bm * zz.y + kk.y * y.y), i0, p.n);
       st2(out, off, o);
@@ -535,7 +668,7 @@ __device__ __forceinline__ void phase_C_matvec(const Prob& p, int m, int rank, i
 }
 
 // s = r - alpha v; partials (s,s), (r^,s); A pass of P^{-1} on s.
-__device__ __forceinline__ void phase_s(const Prob& p, int rank, double alpha, double2* buf) {
+__device__ __forceinline__ void bi_s(const Prob& p, int rank, double alpha, const Lds& L) {
   const Plan& pl = p.pl;
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
@@ -552,18 +685,18 @@ __device__ __forceinline__ void phase_s(const Prob& p, int rank, double alpha, d
         acc[0] += s.x * s.x + s.y * s.y;
         acc[1] += rh.x * s.x + rh.y * s.y;
       }
-      buf[sl] = s;
+      L.bd[sl] = s;
     }
     const int sl[2] = {SL_SS, SL_RS};
     write_partials<2>(p, tile, sl, acc);
-    tileA_fft_store<double>(pl, tile, buf, p.T);
+    tileA_fft_store<double>(pl, tile, L.bd, p.T);
   }
 }
 
 // x += alpha p^ + omega s^; r = s - omega t; p = r + beta (p - omega v);
 // partial (r,r); A pass of P^{-1} on p.
-__device__ __forceinline__ void phase_update(const Prob& p, int m, int rank, double alpha, double omega, double beta,
-                             double2* buf) {
+__device__ __forceinline__ void bi_update(const Prob& p, int m, int rank, double alpha, double omega, double beta,
+                                          const Lds& L) {
   const Plan& pl = p.pl;
   double* x = p.u[m % 3];
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
@@ -588,16 +721,16 @@ __device__ __forceinline__ void phase_update(const Prob& p, int m, int rank, dou
         st2(p.vec[VP], off, pn);
         acc[0] += r.x * r.x + r.y * r.y;
       }
-      buf[sl] = pn;
+      L.bd[sl] = pn;
     }
     const int sl[1] = {SL_RR};
     write_partials<1>(p, tile, sl, acc);
-    tileA_fft_store<double>(pl, tile, buf, p.T);
+    tileA_fft_store<double>(pl, tile, L.bd, p.T);
   }
 }
 
 // x += alpha p^ (half-iteration exit).
-__device__ __forceinline__ void phase_half(const Prob& p, int m, int rank, double alpha) {
+__device__ __forceinline__ void bi_half(const Prob& p, int m, int rank, double alpha) {
   const Plan& pl = p.pl;
   double* x = p.u[m % 3];
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
@@ -616,34 +749,59 @@ __device__ __forceinline__ void phase_half(const Prob& p, int m, int rank, doubl
   }
 }
 
-__device__ __forceinline__ bool bad(double v) { return !isfinite(v); }
-
-// One level of FIDS with right-preconditioned BiCGSTAB (x0 = 0).
-__device__ __forceinline__ int level_bicgstab(const Prob& p, int m, int rank, Ctl& ctl, double* lds_tab, double2* buf) {
-  const size_t nsym = size_t(p.pl.Nc) + 1;
-  const double* Q = p.qhat + size_t(m) * nsym;
-  const double tol = p.tol;
-  phase_soe(p, m, rank, lds_tab, buf);
+// Level setup shared by both solvers: rhs, optional initial residual.
+// bb = ||b||^2, rr0 = ||r0||^2.
+__device__ __forceinline__ int level_start(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L, bool fp32pc,
+                                           double& bb, double& rr0) {
+  if (fp32pc) phase_rhs<float>(p, m, rank, L);
+  else phase_rhs<double>(p, m, rank, L);
   BARRIER();
   double red1[1];
   {
     const int sl[1] = {SL_BB};
     reduce_slots<1>(p, sl, red1);
   }
-  const double bb = red1[0];
-  if (bad(bb)) { write_info(p, rank, m, 0, 0, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
+  bb = red1[0];
+  rr0 = bb;
+  if (p.x0_mode != 0) {
+    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd);
+    BARRIER();
+    if (fp32pc) phase_r0<float>(p, m, rank, L);
+    else phase_r0<double>(p, m, rank, L);
+    BARRIER();
+    const int sl[1] = {SL_RR};
+    reduce_slots<1>(p, sl, red1);
+    rr0 = red1[0];
+  }
+  return FIDS_OK;
+}
+
+// One level of FIDS with right-preconditioned BiCGSTAB.
+__device__ __forceinline__ int level_bicgstab(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L) {
+  const double* Q = pQ<double>(p, m);
+  const double tol = p.tol;
+  double bb, rho;
+  {
+    const int st = level_start(p, m, rank, ctl, L, false, bb, rho);
+    if (st != FIDS_OK) return st;
+  }
+  if (bad(bb) || bad(rho)) { write_info(p, rank, m, 0, 0, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
   const double bnorm = sqrt(bb);
-  if (bb == 0.0) { write_info(p, rank, m, 0, 0, 0.0, FIDS_OK); return FIDS_OK; }
-  double rho = bb, alpha = 0, omega = 0;
-  int it = 0, mv = 0;
+  const int mv0 = p.x0_mode != 0 ? 1 : 0;
+  if (sqrt(rho) <= tol * bnorm) {
+    write_info(p, rank, m, 0, mv0, bnorm > 0 ? sqrt(rho) / bnorm : 0.0, FIDS_OK);
+    return FIDS_OK;
+  }
+  double alpha = 0, omega = 0, red1[1];
+  int it = 0, mv = mv0;
   for (;;) {
-    phase_rows<double>(p, rank, Q, buf);                 // P^{-1} p
+    phase_rows<double, double>(p, rank, Q, p.T, L.bd);   // P^{-1} p
     BARRIER();
-    phase_C_then_A(p, rank, VPH, buf);                   // p^ ; A p^ (column pass)
+    bi_C_then_A(p, rank, VPH, L);                        // p^ ; A p^ (column pass)
     BARRIER();
-    phase_rows<double>(p, rank, p.ahat, buf);
+    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd);
     BARRIER();
-    phase_C_matvec(p, m, rank, 0, buf);                  // v = M p^
+    bi_C_matvec(p, m, rank, 0, L);                       // v = M p^
     BARRIER();
     ++mv;
     {
@@ -654,7 +812,7 @@ __device__ __forceinline__ int level_bicgstab(const Prob& p, int m, int rank, Ct
     if (bad(rv)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
     if (rv == 0.0) { write_info(p, rank, m, it, mv, 1.0, FIDS_ENOCONV); return FIDS_ENOCONV; }
     alpha = rho / rv;
-    phase_s(p, rank, alpha, buf);                        // s = r - alpha v ; P^{-1} s (column pass)
+    bi_s(p, rank, alpha, L);                             // s = r - alpha v ; P^{-1} s (column pass)
     BARRIER();
     double red2[2];
     {
@@ -664,18 +822,18 @@ __device__ __forceinline__ int level_bicgstab(const Prob& p, int m, int rank, Ct
     const double ss = red2[0], rs = red2[1];
     if (bad(ss)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
     if (sqrt(ss) <= tol * bnorm) {
-      phase_half(p, m, rank, alpha);
+      bi_half(p, m, rank, alpha);
       BARRIER();
       write_info(p, rank, m, it + 1, mv, sqrt(ss) / bnorm, FIDS_OK);
       return FIDS_OK;
     }
-    phase_rows<double>(p, rank, Q, buf);
+    phase_rows<double, double>(p, rank, Q, p.T, L.bd);
     BARRIER();
-    phase_C_then_A(p, rank, VSH, buf);
+    bi_C_then_A(p, rank, VSH, L);
     BARRIER();
-    phase_rows<double>(p, rank, p.ahat, buf);
+    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd);
     BARRIER();
-    phase_C_matvec(p, m, rank, 1, buf);                  // t = M s^
+    bi_C_matvec(p, m, rank, 1, L);                       // t = M s^
     BARRIER();
     ++mv;
     ++it;
@@ -691,7 +849,7 @@ __device__ __forceinline__ int level_bicgstab(const Prob& p, int m, int rank, Ct
     const double rho_new = rs - omega * rt;
     if (omega == 0.0) { write_info(p, rank, m, it, mv, sqrt(ss) / bnorm, FIDS_ENOCONV); return FIDS_ENOCONV; }
     const double beta = (rho_new / rho) * (alpha / omega);
-    phase_update(p, m, rank, alpha, omega, beta, buf);   // x, r, p ; P^{-1} p (column pass)
+    bi_update(p, m, rank, alpha, omega, beta, L);        // x, r, p ; P^{-1} p (column pass)
     BARRIER();
     {
       const int sl[1] = {SL_RR};
@@ -708,27 +866,392 @@ __device__ __forceinline__ int level_bicgstab(const Prob& p, int m, int rank, Ct
   }
 }
 
+// ------------------------------------------------------------- FGMRES
+// Small Hessenberg state kept identically by every workgroup (LDS):
+//   hraw[(J+1) x J] unrotated Arnoldi coefficients (row-major, stride J),
+//   cs/sn[J] Givens rotations, g[J+1] rotated right-hand side,
+//   gsave[J] g[j] before rotation j, cor[J+1] re-orthogonalisation
+//   coefficients, y[J+1] least-squares solution / scratch.
+struct Hess {
+  double *hraw, *cs, *sn, *g, *gsave, *cor, *y, *col, *R;
+  int J;
+};
+__device__ __forceinline__ Hess hess(const Lds& L, int J) {
+  Hess H;
+  H.J = J;
+  H.hraw = L.small;
+  H.cs = H.hraw + (J + 1) * J;
+  H.sn = H.cs + J;
+  H.g = H.sn + J;
+  H.gsave = H.g + J + 1;
+  H.cor = H.gsave + J;
+  H.y = H.cor + J + 1;
+  H.col = H.y + J + 1;
+  H.R = H.col + J + 1;        // J x J
+  return H;
+}
+
+// Apply rotations 0..j-1 to column j of hraw, form rotation j, update g.
+// Thread 0 only (state in LDS); callers synchronise.
+__device__ __forceinline__ void givens_col(const Hess& H, int j, bool redo) {
+  double* col = H.col;
+  for (int i = 0; i <= j + 1; ++i) col[i] = H.hraw[i * H.J + j];
+  for (int k = 0; k < j; ++k) {
+    const double a = col[k], b = col[k + 1];
+    col[k] = H.cs[k] * a + H.sn[k] * b;
+    col[k + 1] = -H.sn[k] * a + H.cs[k] * b;
+  }
+  if (!redo) H.gsave[j] = H.g[j];
+  const double a = col[j], b = col[j + 1];
+  const double r = hypot(a, b);
+  const double c = r > 0 ? a / r : 1.0, s = r > 0 ? b / r : 0.0;
+  H.cs[j] = c;
+  H.sn[j] = s;
+  const double gj = H.gsave[j];
+  H.g[j] = c * gj;
+  H.g[j + 1] = -s * gj;
+}
+
+// Back substitution R y = g for columns 0..jl (R rebuilt from hraw by the
+// stored rotations).  Thread 0 only.
+__device__ __forceinline__ void lsq_solve(const Hess& H, int jl) {
+  double* col = H.col;
+  const int J = H.J;
+  for (int j = 0; j <= jl; ++j) {
+    for (int i = 0; i <= j + 1; ++i) col[i] = H.hraw[i * J + j];
+    for (int k = 0; k <= j; ++k) {
+      const double a = col[k], b = col[k + 1];
+      col[k] = H.cs[k] * a + H.sn[k] * b;
+      col[k + 1] = -H.sn[k] * a + H.cs[k] * b;
+    }
+    for (int i = 0; i <= j; ++i) H.R[i * J + j] = col[i];
+  }
+  for (int i = jl; i >= 0; --i) {
+    double s = H.g[i];
+    for (int k = i + 1; k <= jl; ++k) s -= H.R[i * J + k] * H.y[k];
+    H.y[i] = (H.R[i * J + i] != 0.0) ? s / H.R[i * J + i] : 0.0;
+  }
+}
+
+// P1: C pass of A on z_j -> w = b_m' z_j + kappa .* A z_j (stored in VV);
+// re-orthogonalisation of v_j (j >= 1) with cor[] from the previous step;
+// partials (v_i, w), i <= j, and (w, w); then the column pass of P^{-1} on
+// w - v_j.  Pipelining: z_{j+1} is formed in P3 by linearity from
+// P^{-1}(w - v_j) before the Arnoldi coefficients are known.  The shift by
+// v_j matters: with a good preconditioner w ~ v_j, and applying P^{-1} to w
+// itself would amplify its rounding error (FP32 in the mixed form) by
+// ||w|| / eta.
+template <typename RP>
+__device__ __forceinline__ void gm_P1(const Prob& p, int m, int rank, int j, const Lds& L, const Hess& H) {
+  const Plan& pl = p.pl;
+  const double inv = 1.0 / double(pl.Nc);
+  const double bm = p.beta[m];
+  const int vl = p.vlen;
+  for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
+    const TileIdx t = tile_idx(pl, tile);
+    tileC_load_ifft<double>(pl, tile, p.T, L.bd);
+    double accw[1] = {0.0};
+    for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
+      int i0, sl;
+      item(pl, t, idx, i0, sl);
+      const int off = t.toff + 2 * idx;
+      double2 w = make_double2(0.0, 0.0), sh = make_double2(0.0, 0.0);
+      if (i0 < p.n) {
+        const double2 y = cscale<double>(L.bd[sl], inv);
+        const double2 zz = z_get<RP>(p, j, off), kk = ld2(p.kap, off);
+        w = mask2(make_double2(bm * zz.x + kk.x * y.x, bm * zz.y + kk.y * y.y), i0, p.n);
+        double2 v = ld2(p.V + size_t(j) * vl, off);
+        if (j >= 1) {
+          for (int i = 0; i < j; ++i) {
+            const double2 vi = ld2(p.V + size_t(i) * vl, off);
+            v.x -= H.cor[i] * vi.x;
+            v.y -= H.cor[i] * vi.y;
+          }
+          const double sc = 1.0 / H.cor[j];
+          v = make_double2(v.x * sc, v.y * sc);
+          st2(p.V + size_t(j) * vl, off, v);
+        }
+        sh = make_double2(w.x - v.x, w.y - v.y);
+      }
+      st2(p.vec[VV], off, w);
+      accw[0] += w.x * w.x + w.y * w.y;
+      lbuf<RP>(L)[sl] = tocx<RP>(sh);
+    }
+    {
+      const int sl[1] = {SL_GM + kMaxRestart + 1};
+      write_partials<1>(p, tile, sl, accw);
+    }
+    // (v_i, w) in chunks of 8
+    for (int i0b = 0; i0b <= j; i0b += 8) {
+      double acc[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+      for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
+        int i0, sl;
+        item(pl, t, idx, i0, sl);
+        if (i0 >= p.n) continue;
+        const int off = t.toff + 2 * idx;
+        const double2 w = ld2(p.vec[VV], off);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (i0b + q <= j) {
+            const double2 vi = ld2(p.V + size_t(i0b + q) * vl, off);
+            acc[q] += vi.x * w.x + vi.y * w.y;
+          }
+      }
+      block_sum<8>(acc);
+      if (threadIdx.x == 0)
+        for (int q = 0; q < 8 && i0b + q <= j; ++q) p.part[(SL_GM + i0b + q) * pl.ntiles + tile] = acc[q];
+    }
+    tileA_fft_store<RP>(pl, tile, lbuf<RP>(L), pT<RP>(p));
+  }
+}
+
+// P3: C pass of P^{-1} on w - v_j -> y = P^{-1}(w - v_j);
+//   z_{j+1} = (y + z_j - sum_{i<=j} h_ij z_i) / eta,  v_{j+1} = (w - sum h_ij v_i) / eta,
+// stored; partials (v_i, v_{j+1}) i <= j and (v_{j+1}, v_{j+1}) for the
+// re-orthogonalisation; then the column pass of A on z_{j+1}.
+// For j = -1 (start of a cycle): z_0 = y / beta0, v_0 = r0 / beta0.
+template <typename RP>
+__device__ __forceinline__ void gm_P3(const Prob& p, int rank, int j, double eta, const Lds& L, const Hess& H) {
+  const Plan& pl = p.pl;
+  const double inv = 1.0 / double(pl.Nc);
+  const int vl = p.vlen;
+  const double ie = 1.0 / eta;
+  const int jn = j + 1;
+  const double* src = (j < 0) ? p.vec[VR] : p.vec[VV];
+  for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
+    const TileIdx t = tile_idx(pl, tile);
+    tileC_load_ifft<RP>(pl, tile, pT<RP>(p), lbuf<RP>(L));
+    double accv[1] = {0.0};
+    for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
+      int i0, sl;
+      item(pl, t, idx, i0, sl);
+      const int off = t.toff + 2 * idx;
+      double2 z = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
+      if (i0 < p.n) {
+        const double2 y = fromcx<RP>(lbuf<RP>(L)[sl]);
+        z = make_double2(y.x * inv, y.y * inv);
+        if (j >= 0) {
+          const double2 zj = z_get<RP>(p, j, off);
+          z.x += zj.x;
+          z.y += zj.y;
+        }
+        v = ld2(src, off);
+        for (int i = 0; i <= j; ++i) {
+          const double h = H.hraw[i * H.J + j];
+          const double2 zi = z_get<RP>(p, i, off);
+          const double2 vi = ld2(p.V + size_t(i) * vl, off);
+          z.x -= h * zi.x; z.y -= h * zi.y;
+          v.x -= h * vi.x; v.y -= h * vi.y;
+        }
+        z = mask2(make_double2(z.x * ie, z.y * ie), i0, p.n);
+        v = mask2(make_double2(v.x * ie, v.y * ie), i0, p.n);
+        accv[0] += v.x * v.x + v.y * v.y;
+      }
+      L.bd[sl] = z_put<RP>(p, jn, off, z);
+      st2(p.V + size_t(jn) * vl, off, v);
+    }
+    {
+      const int sl[1] = {SL_GM + kMaxRestart + 1};
+      write_partials<1>(p, tile, sl, accv);
+    }
+    for (int i0b = 0; i0b <= j; i0b += 8) {
+      double acc[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+      for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
+        int i0, sl;
+        item(pl, t, idx, i0, sl);
+        if (i0 >= p.n) continue;
+        const int off = t.toff + 2 * idx;
+        const double2 v = ld2(p.V + size_t(jn) * vl, off);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (i0b + q <= j) {
+            const double2 vi = ld2(p.V + size_t(i0b + q) * vl, off);
+            acc[q] += vi.x * v.x + vi.y * v.y;
+          }
+      }
+      block_sum<8>(acc);
+      if (threadIdx.x == 0)
+        for (int q = 0; q < 8 && i0b + q <= j; ++q) p.part[(SL_GM + i0b + q) * pl.ntiles + tile] = acc[q];
+    }
+    tileA_fft_store<double>(pl, tile, L.bd, p.T);
+  }
+}
+
+// F1: x += sum_{i<=jl} y_i z_i; column pass of A on x.
+template <typename RP>
+__device__ __forceinline__ void gm_F1(const Prob& p, int m, int rank, int jl, const Lds& L, const Hess& H) {
+  const Plan& pl = p.pl;
+  double* x = p.u[m % 3];
+  for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
+    const TileIdx t = tile_idx(pl, tile);
+    for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
+      int i0, sl;
+      item(pl, t, idx, i0, sl);
+      const int off = t.toff + 2 * idx;
+      double2 xx = make_double2(0.0, 0.0);
+      if (i0 < p.n) {
+        xx = ld2(x, off);
+        for (int i = 0; i <= jl; ++i) {
+          const double2 zi = z_get<RP>(p, i, off);
+          xx.x += H.y[i] * zi.x;
+          xx.y += H.y[i] * zi.y;
+        }
+        xx = mask2(xx, i0, p.n);
+        st2(x, off, xx);
+      }
+      L.bd[sl] = xx;
+    }
+    tileA_fft_store<double>(pl, tile, L.bd, p.T);
+  }
+}
+
+// One level of FIDS with flexible GMRES(J), right preconditioning, pipelined
+// so that one Arnoldi step costs four group barriers.
+template <typename RP>
+__device__ __forceinline__ int level_fgmres(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L) {
+  const RP* Q = pQ<RP>(p, m);
+  const double tol = p.tol;
+  const int J = p.restart;
+  const Hess H = hess(L, J);
+  double bb, rr;
+  {
+    const int st = level_start(p, m, rank, ctl, L, sizeof(RP) == 4, bb, rr);
+    if (st != FIDS_OK) return st;
+  }
+  if (bad(bb) || bad(rr)) { write_info(p, rank, m, 0, 0, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
+  const double bnorm = sqrt(bb);
+  int it = 0, mv = (p.x0_mode != 0) ? 1 : 0;
+  int floor_hits = 0;       // cycles whose Arnoldi estimate met tol but the true residual did not
+  bool est_conv = false;
+  double red1[1];
+  for (;;) {                                   // restart cycles
+    const double beta0 = sqrt(rr);
+    if (est_conv && beta0 > tol * bnorm && ++floor_hits >= 2) {
+      // the true FP64 residual has reached its attainable floor: accept and
+      // report the true relative residual
+      write_info(p, rank, m, it, mv, beta0 / bnorm, FIDS_OK);
+      return FIDS_OK;
+    }
+    if (beta0 <= tol * bnorm) {
+      write_info(p, rank, m, it, mv, bnorm > 0 ? beta0 / bnorm : 0.0, FIDS_OK);
+      return FIDS_OK;
+    }
+    if (it >= p.maxit) { write_info(p, rank, m, it, mv, beta0 / bnorm, FIDS_ENOCONV); return FIDS_ENOCONV; }
+    if (threadIdx.x == 0) {
+      for (int i = 0; i <= J; ++i) H.g[i] = 0.0;
+      H.g[0] = beta0;
+    }
+    __syncthreads();
+    phase_rows<RP, RP>(p, rank, Q, pT<RP>(p), lbuf<RP>(L));      // P^{-1} r0 (rows)
+    BARRIER();
+    gm_P3<RP>(p, rank, -1, beta0, L, H);                        // z_0, v_0; A z_0 (columns)
+    BARRIER();
+    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd);
+    BARRIER();
+    int jl = 0;
+    for (int j = 0;; ++j) {
+      gm_P1<RP>(p, m, rank, j, L, H);                           // w = M z_j; dots; P^{-1} w (columns)
+      BARRIER();
+      ++it;
+      ++mv;
+      reduce_range(p, SL_GM, j + 1, H.y);                       // h_ij into y[] scratch
+      {
+        const int sl[1] = {SL_GM + kMaxRestart + 1};
+        reduce_slots<1>(p, sl, red1);
+      }
+      double hs = 0.0;
+      for (int i = 0; i <= j; ++i) hs += H.y[i] * H.y[i];
+      if (bad(red1[0]) || bad(hs)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
+      const double e2 = red1[0] - hs;
+      const double eta = e2 > 0.0 ? sqrt(e2) : 0.0;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (int i = 0; i <= j; ++i) H.hraw[i * J + j] = H.y[i];
+        H.hraw[(j + 1) * J + j] = eta;
+        givens_col(H, j, false);
+      }
+      __syncthreads();
+      const double est = fabs(H.g[j + 1]);
+      jl = j;
+      est_conv = est <= tol * bnorm;
+      if (est_conv || j + 1 >= J || eta <= 1e-300 * bnorm || it >= p.maxit) break;
+      phase_rows<RP, RP>(p, rank, Q, pT<RP>(p), lbuf<RP>(L));    // P^{-1} w (rows)
+      BARRIER();
+      gm_P3<RP>(p, rank, j, eta, L, H);                          // z_{j+1}, v_{j+1}; A z_{j+1} (columns)
+      BARRIER();
+      reduce_range(p, SL_GM, j + 1, H.cor);                      // c_i = (v_i, v_{j+1})
+      {
+        const int sl[1] = {SL_GM + kMaxRestart + 1};
+        reduce_slots<1>(p, sl, red1);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double cs = 0.0;
+        for (int i = 0; i <= j; ++i) cs += H.cor[i] * H.cor[i];
+        const double s2 = red1[0] - cs;
+        const double sc = s2 > 0.0 ? sqrt(s2) : 1.0;
+        H.cor[j + 1] = sc;
+        for (int i = 0; i <= j; ++i) H.hraw[i * J + j] += eta * H.cor[i];
+        H.hraw[(j + 1) * J + j] = eta * sc;
+        givens_col(H, j, true);
+      }
+      __syncthreads();
+      phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd);    // A z_{j+1} (rows)
+      BARRIER();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) lsq_solve(H, jl);
+    __syncthreads();
+    gm_F1<RP>(p, m, rank, jl, L, H);                             // x += Z y; A x (columns)
+    BARRIER();
+    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd);
+    BARRIER();
+    if (sizeof(RP) == 4) phase_r0<float>(p, m, rank, L);       // r = b - M x; P^{-1} r (columns)
+    else phase_r0<double>(p, m, rank, L);
+    BARRIER();
+    ++mv;
+    {
+      const int sl[1] = {SL_RR};
+      reduce_slots<1>(p, sl, red1);
+    }
+    rr = red1[0];
+    if (bad(rr)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
+  }
+}
+
 // ------------------------------------------------------------- level kernel
 __global__ void __launch_bounds__(kThreads) k_levels(const Prob* probs, int nprob, int m_begin, int m_end,
                                                      unsigned long long timeout, int* abort_flag) {
   extern __shared__ double2 dyn[];
-  // find this workgroup's problem
   int pid = 0;
   for (int q = 0; q < nprob; ++q)
     if (int(blockIdx.x) >= probs[q].g0) pid = q;
   const Prob& p = probs[pid];
   const int rank = int(blockIdx.x) - p.g0;
   if (rank < 0 || rank >= p.ng) return;
-  double* lds_tab = reinterpret_cast<double*>(dyn);
-  const int tab_c = (3 * p.nexp + 1) / 2;  // in double2 units
-  double2* buf = dyn + tab_c;
+  // LDS: [tab 3*nexp doubles][small][FP64 buffer][FP32 buffer]
+  const int tab_c = (3 * p.nexp + 1) / 2;
+  const int small_c = kSmallDoubles / 2;
+  const int tile_pts = max(2 * p.pl.CT * p.pl.N1, 4 * p.pl.RU * p.pl.N2);
+  Lds L;
+  L.tab = reinterpret_cast<double*>(dyn);
+  L.small = reinterpret_cast<double*>(dyn + tab_c);
+  L.bd = dyn + tab_c + small_c;
+  L.bf = reinterpret_cast<float2*>(L.bd + tile_pts);
   Ctl ctl;
   ctl.gen = 0;
   ctl.timeout = timeout;
   ctl.abort_flag = abort_flag;
   if (threadIdx.x == 0) ctl.gen = __hip_atomic_load(&p.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (int m = m_begin; m <= m_end; ++m) {
-    const int st = level_bicgstab(p, m, rank, ctl, lds_tab, buf);
+    int st;
+    if (p.solver == FIDS_BICGSTAB) st = level_bicgstab(p, m, rank, ctl, L);
+    else if (p.precision == FIDS_MIXED) st = level_fgmres<float>(p, m, rank, ctl, L);
+    else st = level_fgmres<double>(p, m, rank, ctl, L);
     if (st != FIDS_OK) {
       if (rank == 0 && threadIdx.x == 0 && st == FIDS_EDEVICE) p.status[0] = FIDS_EDEVICE;
       return;
@@ -759,6 +1282,7 @@ __global__ void __launch_bounds__(kThreads) k_init_state(const Prob* pp) {
     const int off = t.toff + 2 * idx;
     const double2 v = nat2(p.phi, i0, p.n);
     st2(p.u[0], off, v);
+    st2(p.u[2], off, v);   // u^{-1} := u^0 (level 1 extrapolates to u^0; unused otherwise)
     if (p.store_states) st2(p.uhist, off, v);
   }
 }
@@ -876,13 +1400,16 @@ __global__ void __launch_bounds__(kThreads) k_sym_ones(const SymJob* jj, int m0)
 
 // ------------------------------------------------------------- host launchers
 static size_t plan_lds(const Plan& pl) {
-  const size_t a = size_t(2) * pl.CT * pl.N1, b = size_t(4) * pl.N2;
+  const size_t a = size_t(2) * pl.CT * pl.N1, b = size_t(4) * pl.RU * pl.N2;
   return (a > b ? a : b) * sizeof(double2);
 }
 
 size_t level_lds_bytes(const Prob& h) {
   const size_t tab = size_t((3 * h.nexp + 1) / 2) * sizeof(double2);
-  return tab + plan_lds(h.pl);
+  const size_t small = size_t(kSmallDoubles) * sizeof(double);
+  const size_t bd = plan_lds(h.pl);
+  const size_t bf = (h.precision == FIDS_MIXED) ? bd / 2 : 0;
+  return tab + small + bd + bf;
 }
 
 hipError_t launch_init_state(const Prob& h, const Prob* d, hipStream_t s) {
@@ -912,11 +1439,16 @@ hipError_t launch_symbols(const SymJob& job, const SymJob* d, int m0, int cnt, h
   }
   const size_t lc = plan_lds(job.plc), lr = plan_lds(job.plr);
   hipLaunchKernelGGL(k_sym_a, dim3(job.plc.ntiles, cnt), dim3(kThreads), lc, s, d, m0);
-  hipLaunchKernelGGL(k_sym_b, dim3(job.plc.nunits, cnt), dim3(kThreads), lc, s, d);
+  hipLaunchKernelGGL(k_sym_b, dim3(job.plc.nrg, cnt), dim3(kThreads), lc, s, d);
   hipLaunchKernelGGL(k_sym_c, dim3(job.plc.ntiles, cnt), dim3(kThreads), lc, s, d);
   hipLaunchKernelGGL(k_sym_d, dim3(job.plr.ntiles, cnt), dim3(kThreads), lr, s, d);
-  hipLaunchKernelGGL(k_sym_e, dim3(job.plr.nunits, cnt), dim3(kThreads), lr, s, d, m0);
+  hipLaunchKernelGGL(k_sym_e, dim3(job.plr.nrg, cnt), dim3(kThreads), lr, s, d, m0);
   return hipGetLastError();
+}
+
+hipError_t set_level_lds_limit(size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_levels),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
 hipError_t launch_levels(const Prob* probs, int nprob, int total_wg, size_t lds_bytes, int m_begin,

@@ -29,6 +29,9 @@ hipError_t launch_levels(const Prob* probs, int nprob, int total_wg, size_t lds_
                          int m_begin, int m_end, unsigned long long timeout_ticks,
                          int* abort_flag, hipStream_t s);
 
+// Raises the dynamic-LDS limit of the level kernel.
+hipError_t set_level_lds_limit(size_t bytes);
+
 // Copies u^m (tile-major) into a natural-layout [n] array.
 hipError_t launch_to_natural(const Prob& h, const Prob* d, const double* src, double* dst, hipStream_t s);
 

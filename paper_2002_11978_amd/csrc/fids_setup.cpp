@@ -26,7 +26,7 @@ int validate(const fids_params& p) {
   if (p.precond != FIDS_STRANG && p.precond != FIDS_NONE) return FIDS_EINVAL;
   if (p.x0_mode != 0 && p.x0_mode != 1) return FIDS_EINVAL;
   if (p.wg_count < 0 || p.wg_count > 4096) return FIDS_EINVAL;
-  if (p.n > (int64_t(1) << 26) || p.M > (int64_t(1) << 24)) return FIDS_EINVAL;
+  if (p.n > (int64_t(1) << 21) || p.M > (int64_t(1) << 24)) return FIDS_EINVAL;
   return FIDS_OK;
 }
 

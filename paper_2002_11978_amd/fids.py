@@ -59,6 +59,7 @@ _SIGS = {
     "fids_solve_all": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(StepInfo)]),
     "fids_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "fids_reset": (ctypes.c_int, [_P]),
+    "fids_prepare": (ctypes.c_int, [_P]),
     "fids_destroy": (ctypes.c_int, [_P]),
     "fids_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fids_batch_workspace_size": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32,
@@ -236,6 +237,9 @@ class Problem:
 
     def reset(self):
         _check(lib().fids_reset(self.h), "fids_reset")
+
+    def prepare(self):
+        _check(lib().fids_prepare(self.h), "fids_prepare")
 
     def close(self):
         if getattr(self, "h", None):

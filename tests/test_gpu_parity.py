@@ -18,7 +18,21 @@ from gpu_util import gpu_solve, rel_maxnorm, say
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-8
+TOL = 1e-8          # FP64 paths
+TOL_MIXED = 1e-7    # FP32 preconditioner inside FP64 FGMRES
+
+# (solver, precision, x0_mode) variants of the level solve
+VARIANTS = [
+    pytest.param(dict(solver=0, precision=0, x0_mode=0), id="bicgstab-fp64-x0zero"),
+    pytest.param(dict(solver=0, precision=0, x0_mode=1), id="bicgstab-fp64-x0extrap"),
+    pytest.param(dict(solver=1, precision=0, x0_mode=0), id="fgmres-fp64-x0zero"),
+    pytest.param(dict(solver=1, precision=0, x0_mode=1), id="fgmres-fp64-x0extrap"),
+    pytest.param(dict(solver=1, precision=1, x0_mode=1), id="fgmres-mixed-x0extrap"),
+]
+
+
+def _gate(kw):
+    return TOL_MIXED if kw.get("precision", 0) == 1 else TOL
 
 
 def _oracle(pb):
@@ -51,25 +65,40 @@ def test_table11_first_row_digits_and_iterations():
     assert 6.5 <= its <= 8.5
 
 
+@pytest.mark.parametrize("kw", VARIANTS)
 @pytest.mark.parametrize("n,M", [(1, 4), (2, 3), (5, 1), (100, 12), (257, 9), (1000, 16)])
-def test_ragged_sizes(n, M):
+def test_ragged_sizes(n, M, kw):
     pb = W.seeded(1.5, 0.5, n, M, kappa_seed=1, f_seed=2)
-    U, reps = gpu_solve(pb, soe_tol=1e-11, krylov_tol=1e-13)
+    U, reps = gpu_solve(pb, soe_tol=1e-11, krylov_tol=1e-13, **kw)
     R = _oracle(pb)
     err = rel_maxnorm(U, R)
-    say(f"ragged n={n} M={M}: {err:.3e}")
-    assert err <= TOL
+    say(f"ragged n={n} M={M} {kw}: {err:.3e}")
+    assert err <= _gate(kw)
 
 
+@pytest.mark.parametrize("kw", VARIANTS)
+@pytest.mark.parametrize("wg", [1, 3, 8, 32])
+def test_workgroup_groups(kw, wg):
+    """Several workgroups per problem (group barrier path) against the oracle;
+    n = 4095 gives 64 x 64 four-step tiles."""
+    pb = W.seeded(1.8, 0.6, 4095, 6, kappa_seed=3, f_seed=4)
+    U, reps = gpu_solve(pb, soe_tol=1e-11, krylov_tol=1e-12, wg_count=wg, **kw)
+    R = _oracle(pb)
+    err = rel_maxnorm(U, R)
+    say(f"wg={wg} {kw}: {err:.3e} its {np.mean([r.iters for r in reps]):.2f} mv {np.mean([r.matvecs for r in reps]):.2f}")
+    assert err <= _gate(kw)
+
+
+@pytest.mark.parametrize("kw", VARIANTS)
 @pytest.mark.parametrize("alpha,gamma", [(1.2, 0.3), (1.8, 0.7)])
-def test_seeded_fields_reduced_size(alpha, gamma):
+def test_seeded_fields_reduced_size(alpha, gamma, kw):
     """The seeded-field recipe (8 kappa modes, 16 source modes) at n = 1023."""
     pb = W.seeded(alpha, gamma, 1023, 48, kappa_seed=1, f_seed=2)
-    U, reps = gpu_solve(pb, soe_tol=1e-11, krylov_tol=1e-12)
+    U, reps = gpu_solve(pb, soe_tol=1e-11, krylov_tol=1e-12, **kw)
     R = _oracle(pb)
     err = rel_maxnorm(U, R)
-    say(f"seeded a={alpha} g={gamma}: {err:.3e} its {np.mean([r.matvecs for r in reps]) / 2:.2f}")
-    assert err <= TOL
+    say(f"seeded a={alpha} g={gamma} {kw}: {err:.3e} mv {np.mean([r.matvecs for r in reps]):.2f}")
+    assert err <= _gate(kw)
 
 
 def test_no_preconditioner_same_answer_more_iterations():
