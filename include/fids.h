@@ -54,7 +54,9 @@ extern "C" {
 #define FIDS_EINVAL   -1  /* bad parameter, null pointer, workspace too small     */
 #define FIDS_EDEVICE  -2  /* a HIP runtime call failed                             */
 #define FIDS_ENOCONV  -3  /* Krylov maxit reached or breakdown; the step is not    */
-                          /* advanced and the step info holds iters and relres     */
+                          /* advanced and the step info holds iters and relres.    */
+                          /* After any failed level, stepping again needs          */
+                          /* fids_reset (FIDS_ESTATE until then).                  */
 #define FIDS_ENUMERIC -4  /* NaN/Inf met on the device                             */
 #define FIDS_ESTATE   -5  /* step after M, adjoint without stored forward states  */
 
@@ -95,6 +97,8 @@ typedef struct fids_params {
     int32_t store_states; /* 1: keep every u^m in the workspace (needed by        */
                           /* fids_adjoint); 0: keep only what stepping needs       */
     int32_t wg_count;     /* workgroups that cooperate on one problem; 0 = auto    */
+    int32_t soe_helpers;  /* workgroups that stream the SOE history one level      */
+                          /* ahead of the solve: -1 auto, 0 none, k > 0 exactly k  */
 } fids_params;
 
 /* Per-level report. */
@@ -111,7 +115,8 @@ typedef struct fids_problem fids_problem;
 
 /* Fills *p with: alpha 1.5, gamma 0.5, l 1, T 1, n 255, M 64, r 3, mu 0,
  * soe_tol 1e-10, krylov_tol 1e-12, krylov_maxit 200, restart 20, BiCGSTAB,
- * FP64, Strang, kappa_time_dependent 1, x0_mode 0, store_states 0, wg_count 0. */
+ * FP64, Strang, kappa_time_dependent 1, x0_mode 0, store_states 0, wg_count 0,
+ * soe_helpers -1. */
 int fids_params_default(fids_params* p);
 
 /* Bytes of device workspace the problem needs (256-byte multiple).

@@ -59,12 +59,14 @@ PlanShape plan_shape(int64_t Nc, int target_tiles, int target_groups) {
   return s;
 }
 
-// Workgroups per problem: about one per 2048 packed points (so a pass moves
-// about 32 KiB per workgroup), at most 32 -- the group barrier costs about
-// 1.5 us + 70 ns per workgroup on MI355X.
+// Workgroups per problem: about one per 1024 packed points (a pass moves
+// about 16 KiB per workgroup), at most 64.  The group barrier costs about
+// 1.5 us + 70 ns per workgroup on MI355X, but the work inside a pass (LDS
+// FFT stages, dependent global rounds) dominates, so wider groups win up to
+// this size.
 int default_group(int64_t Nc) {
-  int64_t g = Nc / 2048;
-  return int(std::max<int64_t>(1, std::min<int64_t>(32, g)));
+  int64_t g = Nc / 1024;
+  return int(std::max<int64_t>(1, std::min<int64_t>(64, g)));
 }
 
 int env_int(const char* name, int dflt) {
@@ -79,7 +81,7 @@ struct Layout {
   size_t tw1r, tw1rf, tw2r, tw2rf, tw1c, tw1cf, tw2c, tw2cf, twlo, twlof, twhi, twhif;
   size_t qhat, qhatf;
   size_t Tb, q, Tq;
-  size_t u[3], F, kap, vec[10], uhist, T, Tf, tau, V, Z;
+  size_t u[3], F, kap, vec[10], uhist, T, Tf, tau, V, Z, soec, H1, AU, sync2, hflag;
   size_t total;
   int chunk;
   int twshift;
@@ -100,11 +102,16 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   lo.job = take(sizeof(SymJob));
   lo.abort_ = take(sizeof(int));
   lo.status = take(4 * sizeof(int));
-  lo.bar = take(4 * sizeof(unsigned));
+  lo.bar = take(4096);
   lo.info = take(M * sizeof(fids_step_info));
   lo.part = take(size_t(fids::SL_COUNT) * sh.pr.ntiles * sizeof(double));
   lo.beta = take((M + 1) * 8);
   lo.tau = take((M + 1) * 8);
+  lo.soec = take((M + 1) * 8);
+  // synchronisation words on separate 4 KiB pages (separate memory channels)
+  off = (off + 4095) / 4096 * 4096;
+  lo.sync2 = take(4096);
+  lo.hflag = take(4096 * 64);
   lo.theta = take((M + 1) * ne * 8);
   lo.decay = take((M + 1) * ne * 8);
   lo.gw = take(ne * 8);
@@ -134,6 +141,8 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   for (int i = 0; i < 3; ++i) lo.u[i] = take(L * 8);
   lo.F = take(ne * L * 8);
   lo.kap = take(L * 8);
+  lo.H1 = take(2 * L * 8);
+  lo.AU = take(2 * L * 8);
   for (int i = 0; i < 10; ++i) lo.vec[i] = take(L * 8);
   lo.uhist = p.store_states ? take((M + 1) * L * 8) : 0;
   const bool gm = p.solver == FIDS_FGMRES;
@@ -210,6 +219,7 @@ struct fids_problem {
   int* dstatus = nullptr;
   int64_t level = 0;
   bool symbols_ready = false;
+  bool poisoned = false;     // a level failed: the state is only valid after fids_reset
   size_t lds = 0;
   unsigned long long timeout_ticks = 0;
   // host copies kept alive for asynchronous uploads
@@ -259,13 +269,13 @@ int ensure_symbols(fids_problem* h) {
 }
 
 int run_levels(fids_problem* h, int64_t m_end, fids_step_info* infos_host /*[M] indexed m-1*/) {
-  if (h->level >= h->sh.M) return FIDS_ESTATE;
+  if (h->level >= h->sh.M || h->poisoned) return FIDS_ESTATE;
   int st = ensure_symbols(h);
   if (st != FIDS_OK) return st;
   const int m_begin = int(h->level + 1);
   HIPCHK(hipMemsetAsync(h->dabort, 0, sizeof(int), h->stream));
-  HIPCHK(fids::launch_levels(h->dp, 1, h->hp.ng, h->lds, m_begin, int(m_end), h->timeout_ticks, h->dabort,
-                             h->stream));
+  HIPCHK(fids::launch_levels(h->dp, 1, h->hp.ng + h->hp.nh, h->lds, m_begin, int(m_end), h->timeout_ticks,
+                             h->dabort, h->stream));
   int stat[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(stat, h->dstatus, sizeof(stat), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -277,6 +287,7 @@ int run_levels(fids_problem* h, int64_t m_end, fids_step_info* infos_host /*[M] 
                      size_t(upto - first + 1) * sizeof(fids_step_info), hipMemcpyDeviceToHost));
   }
   if (last >= first) h->level = last;
+  if (stat[0] != FIDS_OK) h->poisoned = true;
   if (stat[0] == FIDS_EDEVICE) {
     // a group barrier timed out: clear the barrier words for the next launch
     HIPCHK(hipMemsetAsync(h->hp.bar, 0, 4 * sizeof(unsigned), h->stream));
@@ -297,6 +308,7 @@ int fids_params_default(fids_params* p) {
   p->soe_tol = 1e-10; p->krylov_tol = 1e-12; p->krylov_maxit = 200; p->restart = 20;
   p->solver = FIDS_BICGSTAB; p->precision = FIDS_FP64; p->precond = FIDS_STRANG;
   p->kappa_time_dependent = 1; p->x0_mode = 0; p->store_states = 0; p->wg_count = 0;
+  p->soe_helpers = -1;
   return FIDS_OK;
 }
 
@@ -346,6 +358,7 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
   // tables
   st |= upload(h, lo.beta, t.beta.data(), t.beta.size() * 8);
   st |= upload(h, lo.tau, t.tau.data(), t.tau.size() * 8);
+  st |= upload(h, lo.soec, t.soec.data(), t.soec.size() * 8);
   st |= upload(h, lo.theta, t.theta.data(), t.theta.size() * 8);
   st |= upload(h, lo.decay, t.decay.data(), t.decay.size() * 8);
   st |= upload(h, lo.gw, t.gw.data(), t.gw.size() * 8);
@@ -376,6 +389,11 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
   fill_plan(hp.pl, h->sh.pr, 2, ws, lo, false);
   hp.g0 = 0;
   hp.ng = std::max(hp.pl.ntiles, hp.pl.nrg);
+  hp.soec = at<double>(ws, lo.soec);
+  hp.H1 = at<double>(ws, lo.H1);
+  hp.AU = at<double>(ws, lo.AU);
+  hp.sync2 = at<unsigned>(ws, lo.sync2);
+  hp.hflag = at<unsigned>(ws, lo.hflag);
   hp.beta = at<double>(ws, lo.beta); hp.tau = at<double>(ws, lo.tau); hp.theta = at<double>(ws, lo.theta); hp.decay = at<double>(ws, lo.decay);
   hp.gw = at<double>(ws, lo.gw); hp.ahat = at<double>(ws, lo.ahat);
   hp.qhat = lo.qhat ? at<double>(ws, lo.qhat) : nullptr;
@@ -408,10 +426,26 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
   j.qhat = const_cast<double*>(hp.qhat); j.qhatf = const_cast<float*>(hp.qhatf);
   j.identity = p->precond == FIDS_NONE;
   h->dj = at<SymJob>(ws, lo.job);
-  if (upload(h, lo.prob, &h->hp, sizeof(Prob)) != FIDS_OK) return fail(FIDS_EDEVICE);
-  if (upload(h, lo.job, &h->hj, sizeof(SymJob)) != FIDS_OK) return fail(FIDS_EDEVICE);
   h->lds = fids::level_lds_bytes(hp);
   if (h->lds > 65536 && fids::set_level_lds_limit(h->lds) != hipSuccess) return fail(FIDS_EDEVICE);
+  {
+    // SOE helpers use the CUs the solver group leaves free (the launch must
+    // stay co-resident)
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        fids::level_max_blocks(h->lds, &per_cu) != hipSuccess)
+      return fail(FIDS_EDEVICE);
+    const int resident = cus * std::max(per_cu, 0);
+    if (resident < hp.ng) return fail(FIDS_EDEVICE);
+    // auto = none: on MI355X at n = 65535 the helpers' stream slowed the
+    // latency-bound solve more than it saved (976 -> 897 levels/s with 128)
+    int nh = p->soe_helpers >= 0 ? p->soe_helpers : env_int("FIDS_HELPERS", 0);
+    nh = std::max(0, std::min({nh, resident - hp.ng, 1024}));   // hflag holds 1024 lines
+    hp.nh = nh;
+  }
+  if (upload(h, lo.prob, &h->hp, sizeof(Prob)) != FIDS_OK) return fail(FIDS_EDEVICE);
+  if (upload(h, lo.job, &h->hj, sizeof(SymJob)) != FIDS_OK) return fail(FIDS_EDEVICE);
   if (fids::launch_init_state(hp, h->dp, h->stream) != hipSuccess) return fail(FIDS_EDEVICE);
   int dev = 0, rate_khz = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(FIDS_EDEVICE);
@@ -426,8 +460,14 @@ int fids_reset(fids_problem* h) {
   if (!h) return FIDS_EINVAL;
   if (fids::launch_init_state(h->hp, h->dp, h->stream) != hipSuccess) return FIDS_EDEVICE;
   HIPCHK(hipMemsetAsync(h->hp.F, 0, size_t(h->hp.nexp) * h->hp.vlen * 8, h->stream));
+  HIPCHK(hipMemsetAsync(h->hp.H1, 0, size_t(2) * h->hp.vlen * 8, h->stream));
+  HIPCHK(hipMemsetAsync(h->hp.sync2, 0, 4096, h->stream));
+  HIPCHK(hipMemsetAsync(h->hp.hflag, 0, 4096 * 64, h->stream));
+  HIPCHK(hipMemsetAsync(h->hp.status, 0, 4 * sizeof(int), h->stream));
+  HIPCHK(hipMemsetAsync(h->hp.bar, 0, 4 * sizeof(unsigned), h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   h->level = 0;
+  h->poisoned = false;
   h->symbols_ready = false;  // every solve from level 0 rebuilds the per-level symbols
   return FIDS_OK;
 }

@@ -75,8 +75,15 @@ struct Prob {
   float2* Tf;                   // FP32 FFT intermediate, Nc complex
   double* part;                 // [SL_COUNT][ntiles]
   fids_step_info* info;         // [M]
-  int* status;                  // [1]
+  int* status;                  // [4]: status, last completed level, stop flag
   unsigned* bar;                // [2] group barrier {count, generation}
+  // SOE helpers: nh workgroups stream the history one level ahead
+  int nh;                       // helper workgroups (0: the solver group streams F itself)
+  const double* soec;           // [M+1] c_m = sum_j g w_j theta_{m,j}
+  double* H1;                   // [2][vlen] sum_j g w_j e^{-s_j tau_m} F_j^{(m-1)}, slot m & 1
+  double* AU;                   // [2][vlen] A u^m of the last two levels, slot m & 1
+  unsigned* sync2;              // [0]: helper step completions, [64]: last completed level
+  unsigned* hflag;              // [nh][64]: per-helper release flags (one 256-byte line each)
 };
 
 // Bluestein / symbol-precompute descriptor (batched over levels).

@@ -155,6 +155,12 @@ __device__ __forceinline__ void tileC_load_ifft(const Plan& pl, int tile, const 
   }
 }
 
+template <typename R, typename RS>
+__device__ __forceinline__ void rowB_point(const Plan& pl, int idx, int u0, const Cx<R>* b0, Cx<R>* b1,
+                                           const RS* S, R s0, R s1, bool have_s, int mode, double* spec,
+                                           float* specf);
+constexpr int kSymRegs = 4;   // kTileCap / kThreads
+
 // row k1 of side s (0 or 1) of row-pair unit u: (u, N1-u), and (0, N1/2) for u = 0.
 __device__ __forceinline__ int unit_row(const Plan& pl, int u, int side) {
   return side == 0 ? u : (u == 0 ? (pl.N1 >> 1) : pl.N1 - u);
@@ -178,8 +184,25 @@ __device__ __forceinline__ void rowB_real(const Plan& pl, int grp, const Cx<R>* 
   const int tot = nrow * N2;
   Cx<R>* b0 = buf;
   Cx<R>* b1 = buf + tot;
+  // the symbol values of this thread's points are fetched with the rows so
+  // that their latency overlaps (at most kTileCap / kThreads points each)
+  R sv0[kSymRegs], sv1[kSymRegs];
   __syncthreads();
-  for (int idx = threadIdx.x; idx < tot; idx += kThreads) {
+#pragma unroll
+  for (int b = 0; b < kSymRegs; ++b) {
+    const int idx = threadIdx.x + b * kThreads;
+    if (idx < tot) {
+      const int q = idx >> pl.log2, n2 = idx & (N2 - 1);
+      const int k1 = unit_row(pl, u0 + (q >> 1), q & 1);
+      b0[idx] = Tin[k1 * N2 + n2];
+      if (mode == 0) {
+        const int k = k1 + N1 * n2;
+        sv0[b] = R(S[k]);
+        sv1[b] = R(S[Nc - k]);
+      }
+    }
+  }
+  for (int idx = threadIdx.x + kSymRegs * kThreads; idx < tot; idx += kThreads) {
     const int q = idx >> pl.log2, n2 = idx & (N2 - 1);
     b0[idx] = Tin[unit_row(pl, u0 + (q >> 1), q & 1) * N2 + n2];
   }
@@ -188,7 +211,34 @@ __device__ __forceinline__ void rowB_real(const Plan& pl, int grp, const Cx<R>* 
     Cx<R>* res = lds_fft<R>(b0, b1, N2, pl.log2, nrow, -1, tw_n2<R>(pl));
     if (res != b0) { b1 = b0; b0 = res; }   // b0: spectrum rows, b1: free
   }
+#pragma unroll
+  for (int b = 0; b < kSymRegs; ++b) {
+    const int idx = threadIdx.x + b * kThreads;
+    if (idx < tot) rowB_point<R, RS>(pl, idx, u0, b0, b1, S, sv0[b], sv1[b], true, mode, spec, specf);
+  }
+  for (int idx = threadIdx.x + kSymRegs * kThreads; idx < tot; idx += kThreads)
+    rowB_point<R, RS>(pl, idx, u0, b0, b1, S, R(0), R(0), false, mode, spec, specf);
+  if (mode != 0) return;
+  __syncthreads();
+  const Cx<R>* res = lds_fft<R>(b1, b0, N2, pl.log2, nrow, +1, tw_n2<R>(pl));
   for (int idx = threadIdx.x; idx < tot; idx += kThreads) {
+    const int q = idx >> pl.log2, n2 = idx & (N2 - 1);
+    const int k1 = unit_row(pl, u0 + (q >> 1), q & 1);
+    Cx<R> v = res[idx];
+    const unsigned e = unsigned(n2 * k1) * unsigned(pl.rootmul);
+    if (e) v = cmulc<R>(v, tw_root<R>(pl, e));
+    Tout[k1 * N2 + n2] = v;
+  }
+}
+
+// One point of the row pass: split the spectrum, apply the symbol (mode 0)
+// or write the real spectrum (mode 1).
+template <typename R, typename RS>
+__device__ __forceinline__ void rowB_point(const Plan& pl, int idx, int u0, const Cx<R>* b0, Cx<R>* b1,
+                                           const RS* S, R s0, R s1, bool have_s, int mode, double* spec,
+                                           float* specf) {
+  const int N1 = pl.N1, N2 = pl.N2, Nc = pl.Nc;
+  {
     const int q = idx >> pl.log2, k2 = idx & (N2 - 1);
     const int u = u0 + (q >> 1);
     const int k1 = unit_row(pl, u, q & 1);
@@ -204,7 +254,7 @@ __device__ __forceinline__ void rowB_real(const Plan& pl, int grp, const Cx<R>* 
     const Cx<R> WO = cmul<R>(W, O);
     const Cx<R> X0 = cadd<R>(E, WO), X1 = csub<R>(E, WO);
     if (mode == 0) {
-      const R s0 = R(S[k]), s1 = R(S[Nc - k]);
+      if (!have_s) { s0 = R(S[k]); s1 = R(S[Nc - k]); }
       const Cx<R> Y0 = cscale<R>(X0, s0), Y1 = cscale<R>(X1, s1);
       const Cx<R> Ep = cscale<R>(cadd<R>(Y0, Y1), R(0.5));
       const Cx<R> Op = cscale<R>(cmulc<R>(csub<R>(Y0, Y1), W), R(0.5));
@@ -217,17 +267,6 @@ __device__ __forceinline__ void rowB_real(const Plan& pl, int grp, const Cx<R>* 
         if (specf) specf[Nc] = float(X1.x);
       }
     }
-  }
-  if (mode != 0) return;
-  __syncthreads();
-  const Cx<R>* res = lds_fft<R>(b1, b0, N2, pl.log2, nrow, +1, tw_n2<R>(pl));
-  for (int idx = threadIdx.x; idx < tot; idx += kThreads) {
-    const int q = idx >> pl.log2, n2 = idx & (N2 - 1);
-    const int k1 = unit_row(pl, u0 + (q >> 1), q & 1);
-    Cx<R> v = res[idx];
-    const unsigned e = unsigned(n2 * k1) * unsigned(pl.rootmul);
-    if (e) v = cmulc<R>(v, tw_root<R>(pl, e));
-    Tout[k1 * N2 + n2] = v;
   }
 }
 
@@ -396,6 +435,14 @@ __device__ __forceinline__ void item(const Plan& pl, const TileIdx& t, int idx, 
 }
 
 __device__ __forceinline__ double2 ld2(const double* a, int off) { return *reinterpret_cast<const double2*>(a + off); }
+// streaming (non-temporal) access for the SOE history, touched once per level
+__device__ __forceinline__ double2 ld2nt(const double* a, size_t off) {
+  return make_double2(__builtin_nontemporal_load(a + off), __builtin_nontemporal_load(a + off + 1));
+}
+__device__ __forceinline__ void st2nt(double* a, size_t off, double2 v) {
+  __builtin_nontemporal_store(v.x, a + off);
+  __builtin_nontemporal_store(v.y, a + off + 1);
+}
 __device__ __forceinline__ void st2(double* a, int off, double2 v) { *reinterpret_cast<double2*>(a + off) = v; }
 __device__ __forceinline__ double2 nat2(const double* a, int i0, int n) {
   return make_double2(i0 < n ? a[i0] : 0.0, i0 + 1 < n ? a[i0 + 1] : 0.0);
@@ -457,6 +504,7 @@ struct Lds {
   double* small;    // FGMRES Hessenberg state
   double2* bd;      // FP64 tile / row buffer
   float2* bf;       // FP32 tile / row buffer
+  Plan pl;          // the problem's plan with its twiddle tables copied to LDS
 };
 template <typename R> __device__ __forceinline__ Cx<R>* lbuf(const Lds& L);
 template <> __device__ __forceinline__ double2* lbuf<double>(const Lds& L) { return L.bd; }
@@ -486,28 +534,132 @@ __device__ __forceinline__ void write_info(const Prob& p, int rank, int m, int i
 __device__ __forceinline__ bool bad(double v) { return !isfinite(v); }
 
 // ------------------------------------------------------------- phases
-// Right-hand side of level m: SOE history update (in place) and
-// b = b_m' u^{m-1} - sum_j g w_j F_j + f^m; kappa^m copied tile-major.
-// Initial guess x0 = 0, or the linear extrapolation
-// u^{m-1} + (tau_m / tau_{m-1}) (u^{m-1} - u^{m-2}) (x0_mode 1).
-// Writes b (VB), x0 (u^m slot), partial (b,b); then either the column pass
-// of P^{-1} on r0 = b (x0 = 0; for BiCGSTAB also r^ = p = b) or the column
-// pass of A on x0.
-template <typename RP>
-__device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const Lds& L) {
+// Wait until *addr >= target (thread 0 polls with agent-scope acquire,
+// sleeping `nap` x 64 cycles between polls); false on timeout, abort, or the
+// solver group's stop flag.
+template <int NAP>
+__device__ __forceinline__ bool wait_ge(const Prob& p, const unsigned* addr, unsigned target, const Ctl& ctl) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned long long t0 = wall_clock64();
+    while (__hip_atomic_load(addr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(NAP);
+      if (__hip_atomic_load(ctl.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+          __hip_atomic_load(&p.status[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
+      if (wall_clock64() - t0 > ctl.timeout) {
+        __hip_atomic_store(ctl.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+    }
+    __threadfence();
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// SOE helper workgroup `hr` of nh: for steps k = k0..k1 it advances the
+// history F^{(k)} = e^{-s tau_k} F^{(k-1)} + theta_k (u^{k-1} - u^{k-2}) over its
+// slice of the elements and forms the next level's history sum
+// H1^{k+1} = sum_j g w_j e^{-s_j tau_{k+1}} F_j^{(k)}, so that level k+1 only needs
+// h = H1^{k+1} + c_{k+1} (u^k - u^{k-1}) (the recurrence split exactly).  Step k
+// starts once level k-1 is complete and every helper has finished step k-1;
+// it runs concurrently with the solve of level k.
+__device__ __forceinline__ int helper_loop(const Prob& p, int hr, int k0, int k1, const Ctl& ctl, double* tab) {
   const Plan& pl = p.pl;
   const int nexp = p.nexp;
+  const int blk = 2 * pl.CT * pl.N1;
+  const int npairs = p.vlen / 2;
+  const int per = (npairs + p.nh - 1) / p.nh;
+  const int q0 = hr * per, q1 = min(npairs, q0 + per);
+  const int logCT = ilog2(pl.CT);
+  double* th = tab;
+  double* de = tab + nexp;
+  double* dn = tab + 2 * nexp;
+  unsigned* myflag = p.hflag + size_t(hr) * 64;
+  for (int k = k0; k <= k1; ++k) {
+    // helper 0 watches the solver group and the other helpers, then releases
+    // each helper through its own flag line (few pollers per address)
+    if (hr == 0) {
+      if (!wait_ge<8>(p, &p.sync2[64], unsigned(k - 1), ctl)) return FIDS_EDEVICE;
+      if (!wait_ge<8>(p, &p.sync2[0], unsigned(k - 2) * unsigned(p.nh), ctl)) return FIDS_EDEVICE;
+      for (int h = threadIdx.x; h < p.nh; h += kThreads)
+        __hip_atomic_store(p.hflag + size_t(h) * 64, unsigned(k), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (!wait_ge<127>(p, myflag, unsigned(k), ctl)) {
+      return FIDS_EDEVICE;
+    }
+    const bool next = k + 1 <= p.M;
+    for (int j = threadIdx.x; j < nexp; j += kThreads) {
+      th[j] = p.theta[size_t(k) * nexp + j];
+      de[j] = p.decay[size_t(k) * nexp + j];
+      dn[j] = next ? p.gw[j] * p.decay[size_t(k + 1) * nexp + j] : 0.0;
+    }
+    __syncthreads();
+    const double* um1 = p.u[(k - 1) % 3];
+    const double* um2 = p.u[(k + 1) % 3];
+    double* H = p.H1 + size_t((k + 1) & 1) * p.vlen;
+    for (int q = q0 + threadIdx.x; q < q1; q += kThreads) {
+      const int tile = (2 * q) / blk, lp = (2 * q) % blk;
+      const int idx = lp >> 1;
+      const int i0 = 2 * (pl.N2 * (idx >> logCT) + tile * pl.CT + (idx & (pl.CT - 1)));
+      if (i0 >= p.n) continue;
+      const int off = 2 * q;
+      const double2 a1 = ld2(um1, off), a2 = ld2(um2, off);
+      const double2 d = make_double2(a1.x - a2.x, a1.y - a2.y);
+      double* Fp = p.F + size_t(tile) * nexp * blk + lp;
+      double2 h = make_double2(0.0, 0.0);
+      for (int j = 0; j < nexp; ++j) {
+        double2 fj = ld2nt(Fp, size_t(j) * blk);
+        fj.x = de[j] * fj.x + th[j] * d.x;
+        fj.y = de[j] * fj.y + th[j] * d.y;
+        st2nt(Fp, size_t(j) * blk, fj);
+        h.x += dn[j] * fj.x;
+        h.y += dn[j] * fj.y;
+      }
+      if (next) st2(H, off, h);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      __hip_atomic_fetch_add(&p.sync2[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  return FIDS_OK;
+}
+
+// Right-hand side of level m (eq. 3.16gu with the SOE history):
+//   b = b_m' u^{m-1} - h^m + f^m,  h^m = sum_j g w_j F_j^{(m)};
+// with helpers h^m = H1^m + c_m (u^{m-1} - u^{m-2}); without them the solver
+// group advances F here.  kappa^m is copied tile-major.
+// Initial guess x0 = 0, or the extrapolation x0 = u^{m-1} + rho (u^{m-1} - u^{m-2}),
+// rho = tau_m / tau_{m-1} (x0_mode 1).  Then one of
+//   fused (FGMRES, x0_mode 1, m >= 3): A x0 = (1+rho) A u^{m-1} - rho A u^{m-2} from
+//     the stored products, r0 = b - b_m' x0 - kappa .* A x0, partials (b,b),
+//     (r0,r0), column pass of P^{-1} on r0;
+//   warm: column pass of A on x0 (the residual follows after the row pass);
+//   cold: r0 = b (BiCGSTAB also r^ = p = b), column pass of P^{-1} on b.
+template <typename RP>
+__device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const Lds& L, bool fused) {
+  const Plan& pl = L.pl;
+  const int nexp = p.nexp;
+  const bool self_soe = p.nh == 0;
   double* th = L.tab;
   double* de = L.tab + nexp;
   double* gw = L.tab + 2 * nexp;
-  __syncthreads();
-  for (int j = threadIdx.x; j < nexp; j += kThreads) {
-    th[j] = p.theta[size_t(m) * nexp + j];
-    de[j] = p.decay[size_t(m) * nexp + j];
-    gw[j] = p.gw[j];
+  if (self_soe) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < nexp; j += kThreads) {
+      th[j] = p.theta[size_t(m) * nexp + j];
+      de[j] = p.decay[size_t(m) * nexp + j];
+      gw[j] = p.gw[j];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const double bm = p.beta[m];
+  const double cm = p.soec[m];
   const double rho = (m >= 2) ? p.tau[m] / p.tau[m - 1] : 0.0;
   const bool warm = p.x0_mode != 0;
   const bool bicg = p.solver == FIDS_BICGSTAB;
@@ -516,15 +668,18 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
   double* x = p.u[m % 3];
   const double* fm = p.f + size_t(m - 1) * p.n;
   const double* km = p.kappa + (p.kappa_td ? size_t(m - 1) * p.n : 0);
+  const double* H1m = p.H1 + size_t(m & 1) * p.vlen;
+  const double* Au1 = p.AU + size_t((m - 1) & 1) * p.vlen;
+  double* Au2 = p.AU + size_t(m & 1) * p.vlen;   // A u^{m-2} in, A x0 out
   const int blk = 2 * pl.CT * pl.N1;
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
-    double acc[1] = {0.0};
+    double acc[2] = {0.0, 0.0};
     for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
       int i0, sl;
       item(pl, t, idx, i0, sl);
       const int off = t.toff + 2 * idx;
-      double2 b = make_double2(0.0, 0.0), x0 = make_double2(0.0, 0.0);
+      double2 b = make_double2(0.0, 0.0), x0 = make_double2(0.0, 0.0), r0 = make_double2(0.0, 0.0);
       if (i0 < p.n) {
         const double2 a1 = ld2(um1, off);
         double2 h = make_double2(0.0, 0.0);
@@ -532,54 +687,77 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
         if (m >= 2) {
           const double2 a2 = ld2(um2, off);
           d = make_double2(a1.x - a2.x, a1.y - a2.y);
-          double* Fp = p.F + size_t(tile) * nexp * blk + 2 * idx;
-          for (int j = 0; j < nexp; ++j) {
-            double2 fj = ld2(Fp, j * blk);
-            fj.x = de[j] * fj.x + th[j] * d.x;
-            fj.y = de[j] * fj.y + th[j] * d.y;
-            st2(Fp, j * blk, fj);
-            h.x += gw[j] * fj.x;
-            h.y += gw[j] * fj.y;
+          if (self_soe) {
+            double* Fp = p.F + size_t(tile) * nexp * blk + 2 * idx;
+            for (int j = 0; j < nexp; ++j) {
+              double2 fj = ld2(Fp, j * blk);
+              fj.x = de[j] * fj.x + th[j] * d.x;
+              fj.y = de[j] * fj.y + th[j] * d.y;
+              st2(Fp, j * blk, fj);
+              h.x += gw[j] * fj.x;
+              h.y += gw[j] * fj.y;
+            }
+          } else {
+            h = make_double2(cm * d.x, cm * d.y);
+            if (m >= 3) {
+              const double2 hh = ld2(H1m, off);
+              h.x += hh.x;
+              h.y += hh.y;
+            }
           }
         }
         const double2 fv = nat2(fm, i0, p.n);
+        const double2 kk = nat2(km, i0, p.n);
         b = mask2(make_double2(bm * a1.x - h.x + fv.x, bm * a1.y - h.y + fv.y), i0, p.n);
         if (warm) x0 = mask2(make_double2(a1.x + rho * d.x, a1.y + rho * d.y), i0, p.n);
-        st2(p.kap, off, nat2(km, i0, p.n));
+        if (fused) {
+          const double2 A1 = ld2(Au1, off), A2 = ld2(Au2, off);
+          const double2 ax = make_double2((1.0 + rho) * A1.x - rho * A2.x, (1.0 + rho) * A1.y - rho * A2.y);
+          st2(Au2, off, mask2(ax, i0, p.n));
+          r0 = mask2(make_double2(b.x - (bm * x0.x + kk.x * ax.x), b.y - (bm * x0.y + kk.y * ax.y)), i0, p.n);
+        }
+        st2(p.kap, off, kk);
         if (p.store_states) st2(p.uhist + size_t(m - 1) * p.vlen, off, a1);
       }
       st2(p.vec[VB], off, b);
       st2(x, off, x0);
-      if (!warm) {
+      acc[0] += b.x * b.x + b.y * b.y;
+      if (fused) {
+        st2(p.vec[VR], off, r0);
+        acc[1] += r0.x * r0.x + r0.y * r0.y;
+        lbuf<RP>(L)[sl] = tocx<RP>(r0);
+      } else if (warm) {
+        L.bd[sl] = x0;
+      } else {
         st2(p.vec[VR], off, b);
         if (bicg) { st2(p.vec[VRH], off, b); st2(p.vec[VP], off, b); }
+        lbuf<RP>(L)[sl] = tocx<RP>(b);
       }
-      acc[0] += b.x * b.x + b.y * b.y;
-      if (warm) L.bd[sl] = x0;
-      else lbuf<RP>(L)[sl] = tocx<RP>(b);
     }
-    const int sl_bb[1] = {SL_BB};
-    write_partials<1>(p, tile, sl_bb, acc);
-    if (warm) tileA_fft_store<double>(pl, tile, L.bd, p.T);
+    const int sls[2] = {SL_BB, SL_RR};
+    write_partials<2>(p, tile, sls, acc);
+    if (warm && !fused) tileA_fft_store<double>(pl, tile, L.bd, p.T);
     else tileA_fft_store<RP>(pl, tile, lbuf<RP>(L), pT<RP>(p));
   }
 }
 
 // Row pass of a symbol over all row groups of the problem.
 template <typename R, typename RS>
-__device__ __forceinline__ void phase_rows(const Prob& p, int rank, const RS* S, Cx<R>* T, Cx<R>* buf) {
-  for (int g = rank; g < p.pl.nrg; g += p.ng) rowB_real<R, RS>(p.pl, g, T, T, S, buf, 0, nullptr, nullptr);
+__device__ __forceinline__ void phase_rows(const Prob& p, int rank, const RS* S, Cx<R>* T, Cx<R>* buf,
+                                           const Lds& L) {
+  for (int g = rank; g < L.pl.nrg; g += p.ng) rowB_real<R, RS>(L.pl, g, T, T, S, buf, 0, nullptr, nullptr);
 }
 
 // Residual r = b - (b_m' x + kappa .* A x) after the row pass of A on x;
-// stores r (and r^ = p = r for BiCGSTAB), partial (r, r), then the column
-// pass of P^{-1} on r.
+// stores r (and r^ = p = r for BiCGSTAB) and A x (as A u^m), partial (r, r),
+// then the column pass of P^{-1} on r.
 template <typename RP>
 __device__ __forceinline__ void phase_r0(const Prob& p, int m, int rank, const Lds& L) {
-  const Plan& pl = p.pl;
+  const Plan& pl = L.pl;
   const double inv = 1.0 / double(pl.Nc);
   const double bm = p.beta[m];
   const double* x = p.u[m % 3];
+  double* Aum = p.AU + size_t(m & 1) * p.vlen;   // A x is kept as A u^m
   const bool bicg = p.solver == FIDS_BICGSTAB;
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
@@ -589,12 +767,13 @@ __device__ __forceinline__ void phase_r0(const Prob& p, int m, int rank, const L
       int i0, sl;
       item(pl, t, idx, i0, sl);
       const int off = t.toff + 2 * idx;
-      double2 r = make_double2(0.0, 0.0);
+      double2 r = make_double2(0.0, 0.0), y = make_double2(0.0, 0.0);
       if (i0 < p.n) {
-        const double2 y = cscale<double>(L.bd[sl], inv);
+        y = mask2(cscale<double>(L.bd[sl], inv), i0, p.n);
         const double2 xx = ld2(x, off), kk = ld2(p.kap, off), b = ld2(p.vec[VB], off);
         r = mask2(make_double2(b.x - (bm * xx.x + kk.x * y.x), b.y - (bm * xx.y + kk.y * y.y)), i0, p.n);
       }
+      st2(Aum, off, y);
       st2(p.vec[VR], off, r);
       if (bicg) { st2(p.vec[VRH], off, r); st2(p.vec[VP], off, r); }
       acc[0] += r.x * r.x + r.y * r.y;
@@ -609,7 +788,7 @@ __device__ __forceinline__ void phase_r0(const Prob& p, int m, int rank, const L
 // ------------------------------------------------------------- BiCGSTAB
 // C pass of P^{-1}: z = crop(IFFT), store z into vec[dst], then A pass of A on z.
 __device__ __forceinline__ void bi_C_then_A(const Prob& p, int rank, int dst, const Lds& L) {
-  const Plan& pl = p.pl;
+  const Plan& pl = L.pl;
   const double inv = 1.0 / double(pl.Nc);
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
@@ -628,7 +807,7 @@ __device__ __forceinline__ void bi_C_then_A(const Prob& p, int rank, int dst, co
 // C pass of A: y = A z;  out = b_m' z + kappa .* y;  partials of dots.
 // which = 0: v = M p^, partial (r^, v).   which = 1: t = M s^, partials (t,s), (t,t), (r^,t).
 __device__ __forceinline__ void bi_C_matvec(const Prob& p, int m, int rank, int which, const Lds& L) {
-  const Plan& pl = p.pl;
+  const Plan& pl = L.pl;
   const double inv = 1.0 / double(pl.Nc);
   const double bm = p.beta[m];
   const double* z = p.vec[which == 0 ? VPH : VSH];
@@ -669,7 +848,7 @@ __device__ __forceinline__ void bi_C_matvec(const Prob& p, int m, int rank, int 
 
 // s = r - alpha v; partials (s,s), (r^,s); A pass of P^{-1} on s.
 __device__ __forceinline__ void bi_s(const Prob& p, int rank, double alpha, const Lds& L) {
-  const Plan& pl = p.pl;
+  const Plan& pl = L.pl;
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
     double acc[2] = {0.0, 0.0};
@@ -697,7 +876,7 @@ __device__ __forceinline__ void bi_s(const Prob& p, int rank, double alpha, cons
 // partial (r,r); A pass of P^{-1} on p.
 __device__ __forceinline__ void bi_update(const Prob& p, int m, int rank, double alpha, double omega, double beta,
                                           const Lds& L) {
-  const Plan& pl = p.pl;
+  const Plan& pl = L.pl;
   double* x = p.u[m % 3];
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
@@ -731,7 +910,7 @@ __device__ __forceinline__ void bi_update(const Prob& p, int m, int rank, double
 
 // x += alpha p^ (half-iteration exit).
 __device__ __forceinline__ void bi_half(const Prob& p, int m, int rank, double alpha) {
-  const Plan& pl = p.pl;
+  const Plan& pl = p.pl;   // sizes only
   double* x = p.u[m % 3];
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
@@ -753,18 +932,22 @@ __device__ __forceinline__ void bi_half(const Prob& p, int m, int rank, double a
 // bb = ||b||^2, rr0 = ||r0||^2.
 __device__ __forceinline__ int level_start(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L, bool fp32pc,
                                            double& bb, double& rr0) {
-  if (fp32pc) phase_rhs<float>(p, m, rank, L);
-  else phase_rhs<double>(p, m, rank, L);
+  // the helpers' history sum H1^m (step m-1) must be complete
+  if (p.nh > 0 && m >= 3 && !wait_ge<8>(p, &p.sync2[0], unsigned(m - 2) * unsigned(p.nh), ctl)) return FIDS_EDEVICE;
+  const bool fused = p.solver == FIDS_FGMRES && p.x0_mode != 0 && m >= 3;
+  if (fp32pc) phase_rhs<float>(p, m, rank, L, fused);
+  else phase_rhs<double>(p, m, rank, L, fused);
   BARRIER();
-  double red1[1];
+  double red2[2];
   {
-    const int sl[1] = {SL_BB};
-    reduce_slots<1>(p, sl, red1);
+    const int sl[2] = {SL_BB, SL_RR};
+    reduce_slots<2>(p, sl, red2);
   }
-  bb = red1[0];
-  rr0 = bb;
-  if (p.x0_mode != 0) {
-    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd);
+  bb = red2[0];
+  rr0 = fused ? red2[1] : bb;
+  double red1[1];
+  if (p.x0_mode != 0 && !fused) {
+    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd, L);
     BARRIER();
     if (fp32pc) phase_r0<float>(p, m, rank, L);
     else phase_r0<double>(p, m, rank, L);
@@ -795,11 +978,11 @@ __device__ __forceinline__ int level_bicgstab(const Prob& p, int m, int rank, Ct
   double alpha = 0, omega = 0, red1[1];
   int it = 0, mv = mv0;
   for (;;) {
-    phase_rows<double, double>(p, rank, Q, p.T, L.bd);   // P^{-1} p
+    phase_rows<double, double>(p, rank, Q, p.T, L.bd, L);   // P^{-1} p
     BARRIER();
     bi_C_then_A(p, rank, VPH, L);                        // p^ ; A p^ (column pass)
     BARRIER();
-    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd);
+    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd, L);
     BARRIER();
     bi_C_matvec(p, m, rank, 0, L);                       // v = M p^
     BARRIER();
@@ -827,11 +1010,11 @@ __device__ __forceinline__ int level_bicgstab(const Prob& p, int m, int rank, Ct
       write_info(p, rank, m, it + 1, mv, sqrt(ss) / bnorm, FIDS_OK);
       return FIDS_OK;
     }
-    phase_rows<double, double>(p, rank, Q, p.T, L.bd);
+    phase_rows<double, double>(p, rank, Q, p.T, L.bd, L);
     BARRIER();
     bi_C_then_A(p, rank, VSH, L);
     BARRIER();
-    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd);
+    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd, L);
     BARRIER();
     bi_C_matvec(p, m, rank, 1, L);                       // t = M s^
     BARRIER();
@@ -943,7 +1126,7 @@ __device__ __forceinline__ void lsq_solve(const Hess& H, int jl) {
 // ||w|| / eta.
 template <typename RP>
 __device__ __forceinline__ void gm_P1(const Prob& p, int m, int rank, int j, const Lds& L, const Hess& H) {
-  const Plan& pl = p.pl;
+  const Plan& pl = L.pl;
   const double inv = 1.0 / double(pl.Nc);
   const double bm = p.beta[m];
   const int vl = p.vlen;
@@ -1014,7 +1197,7 @@ __device__ __forceinline__ void gm_P1(const Prob& p, int m, int rank, int j, con
 // For j = -1 (start of a cycle): z_0 = y / beta0, v_0 = r0 / beta0.
 template <typename RP>
 __device__ __forceinline__ void gm_P3(const Prob& p, int rank, int j, double eta, const Lds& L, const Hess& H) {
-  const Plan& pl = p.pl;
+  const Plan& pl = L.pl;
   const double inv = 1.0 / double(pl.Nc);
   const int vl = p.vlen;
   const double ie = 1.0 / eta;
@@ -1084,7 +1267,7 @@ __device__ __forceinline__ void gm_P3(const Prob& p, int rank, int j, double eta
 // F1: x += sum_{i<=jl} y_i z_i; column pass of A on x.
 template <typename RP>
 __device__ __forceinline__ void gm_F1(const Prob& p, int m, int rank, int jl, const Lds& L, const Hess& H) {
-  const Plan& pl = p.pl;
+  const Plan& pl = L.pl;
   double* x = p.u[m % 3];
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
@@ -1146,11 +1329,11 @@ __device__ __forceinline__ int level_fgmres(const Prob& p, int m, int rank, Ctl&
       H.g[0] = beta0;
     }
     __syncthreads();
-    phase_rows<RP, RP>(p, rank, Q, pT<RP>(p), lbuf<RP>(L));      // P^{-1} r0 (rows)
+    phase_rows<RP, RP>(p, rank, Q, pT<RP>(p), lbuf<RP>(L), L);      // P^{-1} r0 (rows)
     BARRIER();
     gm_P3<RP>(p, rank, -1, beta0, L, H);                        // z_0, v_0; A z_0 (columns)
     BARRIER();
-    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd);
+    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd, L);
     BARRIER();
     int jl = 0;
     for (int j = 0;; ++j) {
@@ -1179,7 +1362,7 @@ __device__ __forceinline__ int level_fgmres(const Prob& p, int m, int rank, Ctl&
       jl = j;
       est_conv = est <= tol * bnorm;
       if (est_conv || j + 1 >= J || eta <= 1e-300 * bnorm || it >= p.maxit) break;
-      phase_rows<RP, RP>(p, rank, Q, pT<RP>(p), lbuf<RP>(L));    // P^{-1} w (rows)
+      phase_rows<RP, RP>(p, rank, Q, pT<RP>(p), lbuf<RP>(L), L);    // P^{-1} w (rows)
       BARRIER();
       gm_P3<RP>(p, rank, j, eta, L, H);                          // z_{j+1}, v_{j+1}; A z_{j+1} (columns)
       BARRIER();
@@ -1200,7 +1383,7 @@ __device__ __forceinline__ int level_fgmres(const Prob& p, int m, int rank, Ctl&
         givens_col(H, j, true);
       }
       __syncthreads();
-      phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd);    // A z_{j+1} (rows)
+      phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd, L);    // A z_{j+1} (rows)
       BARRIER();
     }
     __syncthreads();
@@ -1208,7 +1391,7 @@ __device__ __forceinline__ int level_fgmres(const Prob& p, int m, int rank, Ctl&
     __syncthreads();
     gm_F1<RP>(p, m, rank, jl, L, H);                             // x += Z y; A x (columns)
     BARRIER();
-    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd);
+    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd, L);
     BARRIER();
     if (sizeof(RP) == 4) phase_r0<float>(p, m, rank, L);       // r = b - M x; P^{-1} r (columns)
     else phase_r0<double>(p, m, rank, L);
@@ -1232,36 +1415,76 @@ __global__ void __launch_bounds__(kThreads) k_levels(const Prob* probs, int npro
     if (int(blockIdx.x) >= probs[q].g0) pid = q;
   const Prob& p = probs[pid];
   const int rank = int(blockIdx.x) - p.g0;
-  if (rank < 0 || rank >= p.ng) return;
-  // LDS: [tab 3*nexp doubles][small][FP64 buffer][FP32 buffer]
+  if (rank < 0 || rank >= p.ng + p.nh) return;
+  // LDS: [tab 3*nexp doubles][small][twiddles FP64][twiddles FP32][FP64 buffer][FP32 buffer]
   const int tab_c = (3 * p.nexp + 1) / 2;
   const int small_c = kSmallDoubles / 2;
   const int tile_pts = max(2 * p.pl.CT * p.pl.N1, 4 * p.pl.RU * p.pl.N2);
+  const int nlo = p.pl.twmask + 1, nhi = p.L >> p.pl.twshift;
+  const int ntw = p.pl.N1 + p.pl.N2 + nlo + nhi;
+  const bool mixed = p.precision == FIDS_MIXED;
   Lds L;
   L.tab = reinterpret_cast<double*>(dyn);
   L.small = reinterpret_cast<double*>(dyn + tab_c);
-  L.bd = dyn + tab_c + small_c;
+  double2* twd = dyn + tab_c + small_c;
+  float2* twf = reinterpret_cast<float2*>(twd + ntw);
+  L.bd = twd + ntw + (mixed ? (ntw + 1) / 2 : 0);
   L.bf = reinterpret_cast<float2*>(L.bd + tile_pts);
+  L.pl = p.pl;
+  {
+    const Plan& g = p.pl;
+    for (int i = threadIdx.x; i < ntw; i += kThreads) {
+      double2 v;
+      float2 vf = make_float2(0.f, 0.f);
+      if (i < g.N1) { v = g.tw1[i]; if (mixed) vf = g.tw1f[i]; }
+      else if (i < g.N1 + g.N2) { v = g.tw2[i - g.N1]; if (mixed) vf = g.tw2f[i - g.N1]; }
+      else if (i < g.N1 + g.N2 + nlo) { v = g.twlo[i - g.N1 - g.N2]; if (mixed) vf = g.twlof[i - g.N1 - g.N2]; }
+      else { v = g.twhi[i - g.N1 - g.N2 - nlo]; if (mixed) vf = g.twhif[i - g.N1 - g.N2 - nlo]; }
+      twd[i] = v;
+      if (mixed) twf[i] = vf;
+    }
+    L.pl.tw1 = twd;
+    L.pl.tw2 = twd + g.N1;
+    L.pl.twlo = twd + g.N1 + g.N2;
+    L.pl.twhi = twd + g.N1 + g.N2 + nlo;
+    L.pl.tw1f = twf;
+    L.pl.tw2f = twf + g.N1;
+    L.pl.twlof = twf + g.N1 + g.N2;
+    L.pl.twhif = twf + g.N1 + g.N2 + nlo;
+    __syncthreads();
+  }
   Ctl ctl;
   ctl.gen = 0;
   ctl.timeout = timeout;
   ctl.abort_flag = abort_flag;
   if (threadIdx.x == 0) ctl.gen = __hip_atomic_load(&p.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (rank >= p.ng) {                         // SOE helper
+    helper_loop(p, rank - p.ng, max(2, m_begin - 1), m_end - 1, ctl, L.tab);
+    return;
+  }
   for (int m = m_begin; m <= m_end; ++m) {
     int st;
     if (p.solver == FIDS_BICGSTAB) st = level_bicgstab(p, m, rank, ctl, L);
     else if (p.precision == FIDS_MIXED) st = level_fgmres<float>(p, m, rank, ctl, L);
     else st = level_fgmres<double>(p, m, rank, ctl, L);
     if (st != FIDS_OK) {
-      if (rank == 0 && threadIdx.x == 0 && st == FIDS_EDEVICE) p.status[0] = FIDS_EDEVICE;
+      if (rank == 0 && threadIdx.x == 0) {
+        if (st == FIDS_EDEVICE) p.status[0] = FIDS_EDEVICE;
+        __hip_atomic_store(&p.status[2], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
       return;
+    }
+    // level m is complete in every workgroup of the group: publish it
+    if (rank == 0 && threadIdx.x == 0) {
+      __threadfence();
+      __hip_atomic_store(&p.sync2[64], unsigned(m), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   // keep u^M with the stored states (tile-local copy, no barrier needed)
   if (p.store_states && m_end == p.M) {
     const double* uM = p.u[p.M % 3];
-    for (int tile = rank; tile < p.pl.ntiles; tile += p.ng) {
-      const TileIdx t = tile_idx(p.pl, tile);
+    for (int tile = rank; tile < L.pl.ntiles; tile += p.ng) {
+      const TileIdx t = tile_idx(L.pl, tile);
       for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
         const int off = t.toff + 2 * idx;
         st2(p.uhist + size_t(p.M) * p.vlen, off, ld2(uM, off));
@@ -1408,8 +1631,11 @@ size_t level_lds_bytes(const Prob& h) {
   const size_t tab = size_t((3 * h.nexp + 1) / 2) * sizeof(double2);
   const size_t small = size_t(kSmallDoubles) * sizeof(double);
   const size_t bd = plan_lds(h.pl);
-  const size_t bf = (h.precision == FIDS_MIXED) ? bd / 2 : 0;
-  return tab + small + bd + bf;
+  const bool mixed = h.precision == FIDS_MIXED;
+  const size_t bf = mixed ? bd / 2 : 0;
+  const size_t ntw = size_t(h.pl.N1) + h.pl.N2 + size_t(h.pl.twmask + 1) + (size_t(h.L) >> h.pl.twshift);
+  const size_t tw = ntw * sizeof(double2) + (mixed ? ((ntw + 1) / 2) * sizeof(double2) : 0);
+  return tab + small + tw + bd + bf;
 }
 
 hipError_t launch_init_state(const Prob& h, const Prob* d, hipStream_t s) {
@@ -1444,6 +1670,11 @@ hipError_t launch_symbols(const SymJob& job, const SymJob* d, int m0, int cnt, h
   hipLaunchKernelGGL(k_sym_d, dim3(job.plr.ntiles, cnt), dim3(kThreads), lr, s, d);
   hipLaunchKernelGGL(k_sym_e, dim3(job.plr.nrg, cnt), dim3(kThreads), lr, s, d, m0);
   return hipGetLastError();
+}
+
+hipError_t level_max_blocks(size_t lds_bytes, int* per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, reinterpret_cast<const void*>(k_levels), kThreads,
+                                                      lds_bytes);
 }
 
 hipError_t set_level_lds_limit(size_t bytes) {

@@ -29,6 +29,9 @@ hipError_t launch_levels(const Prob* probs, int nprob, int total_wg, size_t lds_
                          int m_begin, int m_end, unsigned long long timeout_ticks,
                          int* abort_flag, hipStream_t s);
 
+// Co-resident workgroups of the level kernel per CU for a given LDS size.
+hipError_t level_max_blocks(size_t lds_bytes, int* per_cu);
+
 // Raises the dynamic-LDS limit of the level kernel.
 hipError_t set_level_lds_limit(size_t bytes);
 

@@ -26,6 +26,7 @@ int validate(const fids_params& p) {
   if (p.precond != FIDS_STRANG && p.precond != FIDS_NONE) return FIDS_EINVAL;
   if (p.x0_mode != 0 && p.x0_mode != 1) return FIDS_EINVAL;
   if (p.wg_count < 0 || p.wg_count > 4096) return FIDS_EINVAL;
+  if (p.soe_helpers < -1 || p.soe_helpers > 4096) return FIDS_EINVAL;
   if (p.n > (int64_t(1) << 21) || p.M > (int64_t(1) << 24)) return FIDS_EINVAL;
   return FIDS_OK;
 }
@@ -329,6 +330,12 @@ int build_tables(const fids_params& p, HostTables& t) {
         t.theta[size_t(m) * t.nexp + j] = e * (x > 0 ? -std::expm1(-x) / x : 1.0);
       }
     }
+  t.soec.assign(p.M + 1, 0.0);
+  for (int64_t m = 2; m <= p.M; ++m) {
+    long double c = 0;
+    for (int j = 0; j < t.nexp; ++j) c += (long double)t.gw[j] * t.theta[size_t(m) * t.nexp + j];
+    t.soec[m] = double(c);
+  }
   t.col = ifl_column(p.n, p.alpha, p.l, mu);
   // symbol of the L-circulant whose leading n x n block is A
   {

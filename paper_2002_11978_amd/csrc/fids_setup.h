@@ -33,6 +33,7 @@ struct HostTables {
   std::vector<double> theta;   // [(M+1) * nexp], recurrence input factor (m >= 2)
   std::vector<double> decay;   // [(M+1) * nexp], e^{-s_j tau_m}
   std::vector<double> gw;      // [nexp], g w_j
+  std::vector<double> soec;    // [M+1], c_m = sum_j g w_j theta_{m,j}
   SoeNodes soe;
   std::vector<double> col;     // [n], first column of A
   std::vector<double> ahat;    // [Nc+1], real symbol of A's L-circulant embedding

@@ -32,6 +32,7 @@ class Params(ctypes.Structure):
         ("restart", ctypes.c_int32), ("solver", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("precond", ctypes.c_int32), ("kappa_time_dependent", ctypes.c_int32),
         ("x0_mode", ctypes.c_int32), ("store_states", ctypes.c_int32), ("wg_count", ctypes.c_int32),
+        ("soe_helpers", ctypes.c_int32),
     ]
 
 

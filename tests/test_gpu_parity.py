@@ -101,6 +101,32 @@ def test_seeded_fields_reduced_size(alpha, gamma, kw):
     assert err <= _gate(kw)
 
 
+@pytest.mark.parametrize("kw", VARIANTS)
+@pytest.mark.parametrize("helpers", [0, 1, 5, 16])
+def test_soe_helpers(kw, helpers):
+    """SOE history streamed by helper workgroups one level ahead of the solve
+    (the history sum split exactly) against the oracle, several group sizes."""
+    pb = W.seeded(1.6, 0.4, 2047, 24, kappa_seed=3, f_seed=4)
+    U, reps = gpu_solve(pb, soe_tol=1e-11, krylov_tol=1e-12, soe_helpers=helpers, wg_count=4, **kw)
+    R = _oracle(pb)
+    err = rel_maxnorm(U, R)
+    say(f"helpers={helpers} {kw}: {err:.3e}")
+    assert err <= _gate(kw)
+
+
+def test_step_by_step_with_helpers_matches_solve_all():
+    from paper_2002_11978_amd import fids
+    from gpu_util import to_dev
+    pb = W.seeded(1.6, 0.4, 2047, 12, kappa_seed=3, f_seed=4)
+    kw = dict(solver=1, precision=0, x0_mode=1, soe_helpers=8, wg_count=4)
+    U1, _ = gpu_solve(pb, **kw)
+    params = fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=pb.M, r=pb.r, **kw)
+    prob = fids.Problem(params, to_dev(pb.kappa), to_dev(pb.f), to_dev(pb.phi))
+    for m in range(1, pb.M + 1):
+        u, rep = prob.step()
+        assert np.array_equal(u.cpu().numpy(), U1[m]), m
+
+
 def test_no_preconditioner_same_answer_more_iterations():
     pb = W.example2(1.9, 0.5, 2, 64, 40)
     Up, rp = gpu_solve(pb, soe_tol=1e-10, krylov_tol=1e-12)
