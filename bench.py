@@ -1,14 +1,23 @@
 """Benchmark: solved time levels per second of the fast implicit difference
 scheme on one MI355X, at n = 65535 interior nodes and M = 2048 graded levels
 (alpha = 1.5, gamma = 0.4, r = (2-gamma)/gamma = 4, seeded smooth kappa(x,t)
-and f(x,t), phi = (1-x^2)^{alpha/2}).
+and f(x,t), phi = (1-x^2)^{alpha/2}; SOE tolerance 1e-10, Krylov tolerance
+1e-10 relative to ||b||, the tolerance of the paper's Table 11).
 
-A bench "step" is one time level: the SOE history update and right-hand side,
-the level's Strang preconditioner symbol, and the preconditioned Krylov solve.
-The timed region starts from level 0 (inputs resident in HBM, tables built)
-and runs exactly --steps levels, restarting from level 0 after level M.
+A bench "step" is one time level: the SOE history update and right-hand
+side, the level's Strang preconditioner symbol, and the preconditioned
+Krylov solve.  The timed region starts from level 0 (inputs resident in HBM,
+set-up tables built) and runs exactly --steps levels, restarting from level 0
+after level M; it includes the per-level symbol construction.
 
-Prints one JSON line.  Extra fields:
+Three forms of the same scheme are measured:
+  headline  flexible GMRES(20), FP64, extrapolated initial guess
+  plain     BiCGSTAB, FP64, zero initial guess (the paper's solver settings)
+  mixed     flexible GMRES(20) with the preconditioner FFTs in FP32
+`value` is the headline form; the others are reported beside it together with
+the relative difference of their u(T) from the headline's.
+
+Extra JSON fields:
   roofline      algorithmic HBM bytes of the level kernel / its measured time
   cpu_baseline  the CPU oracle (direct scheme, dense LU) on a bounded sample
 """
@@ -25,6 +34,12 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 
+FORMS = {
+    "headline": dict(solver=1, precision=0, x0_mode=1, label="fgmres(20)-fp64-x0extrap"),
+    "plain": dict(solver=0, precision=0, x0_mode=0, label="bicgstab-fp64-x0zero"),
+    "mixed": dict(solver=1, precision=1, x0_mode=1, label="fgmres(20)-fp64/fp32pc-x0extrap"),
+}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -33,8 +48,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2048)
     ap.add_argument("--n", type=int, default=65535)
     ap.add_argument("--M", type=int, default=2048)
-    ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "fgmres"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--forms", default="headline,plain,mixed")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-levels", type=int, default=24)
     ap.add_argument("--cpu-n", type=int, default=4095)
@@ -43,155 +58,197 @@ def parse():
 
 def workload(n, M):
     from paper_2002_11978_amd import workloads as W
-    return W.seeded(1.5, 0.4, n, M, r=4.0, kappa_seed=3, f_seed=4, name="c2")
+    return W.seeded(1.5, 0.4, n, M, r=4.0, kappa_seed=3, f_seed=4, name="bench")
 
 
-def algorithmic_bytes_per_level(n, nexp, matvecs):
-    """Compulsory HBM bytes of one level (FP64 = 8 B; each vector read or
-    written once per use in the method, symbols counted as n values):
-      SOE update + rhs: read/write F (16 n nexp), read u^{m-1}, u^{m-2}, f^m,
-                        kappa^m and write b (40 n)
-      per BiCGSTAB iteration (two matvecs): 280 n
+def level_bytes(form, n, nexp, iters, matvecs, restart=20):
+    """Compulsory HBM bytes of one level (FP64 8 B per value; every vector is
+    read or written once per use in the method; symbols count n values):
+      SOE update + right-hand side: F read and written (16 n nexp), u^{m-1},
+        u^{m-2}, f^m, kappa^m read and b written (40 n);
+      BiCGSTAB, per iteration (2 matvecs, 2 preconditioner applications, 7
+        dot products, 4 vector updates): 280 n;
+      FGMRES, Arnoldi step j (0-based within a cycle): matvec 32 n, P^{-1}
+        apply 24 n, dots with v_0..v_j 8 n (j+1), forming z_{j+1} and v_{j+1}
+        from z_0..z_j, v_0..v_j 16 n (j+1) + 24 n, re-orthogonalisation dots
+        8 n (j+2); plus per level the update x += Z y (8 n (it+2)) and the
+        true residual (48 n).
     """
-    return 16.0 * n * nexp + 40.0 * n + 140.0 * n * matvecs
+    b = 16.0 * n * nexp + 40.0 * n
+    if FORMS[form]["solver"] == 0:
+        return b + 140.0 * n * matvecs
+    zb = 4.0 if FORMS[form]["precision"] == 1 else 8.0
+    for i in range(iters):
+        j = i % restart
+        b += 32 * n + 24 * n + 8 * n * (j + 1) + (8 + zb) * n * (j + 1) + 24 * n + 8 * n * (j + 2)
+    b += zb * n * (min(iters, restart) + 2) + 48.0 * n
+    return b
 
 
 def cpu_baseline(args):
     """Oracle (direct scheme, dense LU per level, full history) on the first
     levels of the same recipe at n = cpu_n; reported in levels/s."""
+    import scipy.linalg as sla
+
     import oracle
-    import torch
-    t_threads = torch.get_num_threads()
     pb = workload(args.cpu_n, args.M)
     K = args.cpu_levels
-    kap = pb.kappa[:K]
-    f = pb.f[:K]
     t0 = time.perf_counter()
-    # run the direct scheme over the first K levels of the M-level mesh
     A = oracle.ifl_matrix(pb.n, pb.alpha)
     g = 1.0 / math.gamma(1.0 - pb.gamma)
     U = np.empty((K + 1, pb.n))
     U[0] = pb.phi
-    import scipy.linalg as sla
     for m in range(1, K + 1):
         a = oracle.l1_weights(1.0, pb.M, pb.r, pb.gamma, m)
-        rhs = g * a[0] * U[0] + f[m - 1]
+        rhs = g * a[0] * U[0] + pb.f[m - 1]
         if m > 1:
             rhs = rhs + g * (np.diff(a)[: m - 1] @ U[1:m])
-        Mm = kap[m - 1][:, None] * A
+        Mm = pb.kappa[m - 1][:, None] * A
         Mm[np.diag_indices(pb.n)] += g * a[m - 1]
         U[m] = sla.solve(Mm, rhs)
     dt = time.perf_counter() - t0
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     return {"value": K / dt, "unit": "levels/s", "cores": cores, "kind": "oracle",
-            "sample": f"direct scheme + LAPACK dense LU, first {K} of M={pb.M} levels of the same recipe "
-                      f"at n={pb.n} (n=65535 does not fit a dense LU in a bounded time); "
-                      f"{dt:.1f} s; torch threads {t_threads}"}
+            "sample": f"direct scheme + LAPACK dense LU (all host threads), first {K} of M={pb.M} levels of the "
+                      f"same recipe at n={pb.n}; a dense LU at n=65535 does not fit a bounded run; {dt:.1f} s"}
+
+
+class Runner:
+    def __init__(self, pb, form, tol, dev):
+        import torch
+
+        from paper_2002_11978_amd import fids
+        self.fids, self.torch = fids, torch
+        cfg = {k: v for k, v in FORMS[form].items() if k != "label"}
+        self.params = fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=pb.M, r=pb.r,
+                                          soe_tol=1e-10, krylov_tol=tol, krylov_maxit=500,
+                                          kappa_time_dependent=1, **cfg)
+        self.prob = fids.Problem(self.params, pb.kappa_d, pb.f_d, pb.phi_d)
+        self.M = pb.M
+        self.infos = (fids.StepInfo * pb.M)()
+
+    def levels(self, K):
+        """Exactly K levels from level 0, wrapping at M."""
+        done = 0
+        while done < K:
+            self.prob.reset()
+            if K - done >= self.M:
+                st = self.prob.solve_all_raw(None, None, self.infos)
+                if st != 0:
+                    raise self.fids.FidsError(st, "fids_solve_all")
+                done += self.M
+            else:
+                for _ in range(K - done):
+                    self.prob.step()
+                done = K
+
+    def timed(self, K, W):
+        torch = self.torch
+        if W > 0:
+            self.levels(W)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(self.prob.stream)
+        self.levels(K)
+        e1.record(self.prob.stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, e0.elapsed_time(e1)
+
+    def kernel_only(self):
+        """One launch of the level kernel over all M levels (symbols prepared)."""
+        torch = self.torch
+        self.prob.reset()
+        self.prob.prepare()
+        torch.cuda.synchronize()
+        k0 = torch.cuda.Event(enable_timing=True)
+        k1 = torch.cuda.Event(enable_timing=True)
+        k0.record(self.prob.stream)
+        st = self.prob.solve_all_raw(None, None, self.infos)
+        k1.record(self.prob.stream)
+        torch.cuda.synchronize()
+        if st != 0:
+            raise self.fids.FidsError(st, "fids_solve_all")
+        return k0.elapsed_time(k1)
+
+    def final_state(self):
+        self.prob.reset()
+        uT, _, reps = self.prob.solve_all()
+        return uT.cpu().numpy(), reps
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "independent problems shard across GPUs without communication, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); independent problems shard "
+              "across GPUs without communication", file=sys.stderr)
         sys.exit(2)
     import torch
+
     from paper_2002_11978_amd import fids
 
     dev = torch.device("cuda:0")
     pb = workload(args.n, args.M)
-    solver = fids.FIDS_FGMRES if args.solver == "fgmres" else fids.FIDS_BICGSTAB
-    prec = fids.FIDS_MIXED if args.precision == "mixed" else fids.FIDS_FP64
-    params = fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=pb.M, r=pb.r,
-                                 soe_tol=1e-10, krylov_tol=1e-12, krylov_maxit=500,
-                                 solver=solver, precision=prec, kappa_time_dependent=1)
-    kappa = torch.from_numpy(pb.kappa).to(dev)
-    f = torch.from_numpy(pb.f).to(dev)
-    phi = torch.from_numpy(pb.phi).to(dev)
-    prob = fids.Problem(params, kappa, f, phi)
-    stream = prob.stream
-    M = pb.M
-    infos = (fids.StepInfo * M)()
-
-    def run_levels(K):
-        """Exactly K levels from level 0, wrapping at M."""
-        done = 0
-        while done < K:
-            prob.reset()
-            if K - done >= M:
-                st = prob.solve_all_raw(None, None, infos)
-                if st != 0:
-                    raise fids.FidsError(st, "fids_solve_all")
-                done += M
-            else:
-                for _ in range(K - done):
-                    prob.step()
-                done = K
-
-    print(f"[bench] n={pb.n} M={M} ws={prob.ws_bytes / 2**20:.1f} MiB warmup={args.warmup} steps={args.steps}",
-          file=sys.stderr, flush=True)
-    if args.warmup > 0:
-        run_levels(args.warmup)
-    torch.cuda.synchronize()
-    # ---- timed region: exactly K levels
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    run_levels(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = e0.elapsed_time(e1)
-    value = args.steps / wall
-    print(f"[bench] {args.steps} levels in {wall:.3f} s wall ({ms_total:.1f} ms events)", file=sys.stderr, flush=True)
-
-    # ---- level kernel alone: symbols prepared first, one launch for all M levels
-    prob.reset()
-    prob.prepare()
-    torch.cuda.synchronize()
-    k0 = torch.cuda.Event(enable_timing=True)
-    k1 = torch.cuda.Event(enable_timing=True)
-    k0.record(stream)
-    st = prob.solve_all_raw(None, None, infos)
-    k1.record(stream)
-    torch.cuda.synchronize()
-    if st != 0:
-        raise fids.FidsError(st, "fids_solve_all")
-    kern_ms = k0.elapsed_time(k1)
-    mv = [infos[i].matvecs for i in range(M)]
-    nexp = int(fids.soe_nodes(pb.gamma, (1.0 / M) ** pb.r, 1.0, params.soe_tol)[0].size)
-    bytes_launch = sum(algorithmic_bytes_per_level(pb.n, nexp, v) for v in mv)
-    achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
-    print(f"[bench] level kernel {kern_ms:.1f} ms for {M} levels; nexp={nexp}; "
-          f"avg its {np.mean(mv) / 2:.2f}; {bytes_launch / 1e9:.2f} GB algorithmic", file=sys.stderr, flush=True)
-
+    pb.kappa_d = torch.from_numpy(pb.kappa).to(dev)
+    pb.f_d = torch.from_numpy(pb.f).to(dev)
+    pb.phi_d = torch.from_numpy(pb.phi).to(dev)
+    nexp = int(fids.soe_nodes(pb.gamma, (1.0 / pb.M) ** pb.r, 1.0, 1e-10)[0].size)
+    forms = [f for f in args.forms.split(",") if f]
+    res = {}
+    ref_uT = None
+    for form in forms:
+        run = Runner(pb, form, args.tol, dev)
+        steps = args.steps if form == "headline" else pb.M
+        warm = args.warmup if form == "headline" else min(args.warmup, 256)
+        print(f"[bench] {form}: n={pb.n} M={pb.M} ws={run.prob.ws_bytes / 2**20:.0f} MiB "
+              f"warmup={warm} steps={steps}", file=sys.stderr, flush=True)
+        wall, ev_ms = run.timed(steps, warm)
+        kern_ms = run.kernel_only()
+        mv = np.array([run.infos[i].matvecs for i in range(pb.M)])
+        it = np.array([run.infos[i].iters for i in range(pb.M)])
+        rr = np.array([run.infos[i].relres for i in range(pb.M)])
+        nbytes = float(sum(level_bytes(form, pb.n, nexp, int(it[i]), int(mv[i])) for i in range(pb.M)))
+        uT, _ = run.final_state()
+        if ref_uT is None:
+            ref_uT = uT
+        res[form] = dict(value=steps / wall, ms_per_step=wall * 1e3 / steps, event_ms=ev_ms,
+                         kernel_ms=kern_ms, bytes=nbytes, avg_iters=float(it.mean()),
+                         avg_matvecs=float(mv.mean()), relres_max=float(rr.max()),
+                         uT_rel_diff=float(np.max(np.abs(uT - ref_uT)) / np.max(np.abs(ref_uT))),
+                         label=FORMS[form]["label"])
+        print(f"[bench] {form}: {res[form]['value']:.1f} levels/s, kernel {kern_ms:.1f} ms, "
+              f"its {it.mean():.2f}, matvecs {mv.mean():.2f}, relres_max {rr.max():.2e}, "
+              f"uT diff {res[form]['uT_rel_diff']:.2e}", file=sys.stderr, flush=True)
+        run.prob.close()
+    head = res[forms[0]]
+    achieved = head["bytes"] / (head["kernel_ms"] * 1e-3) / 1e9
     out = {
         "metric": "solved time steps/s at N=65535,M=2048",
-        "value": value,
+        "value": head["value"],
         "unit": "time steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == fids.FIDS_FP64 else "f64+f32",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"fractional diffusion, n={pb.n} interior nodes, M={M} graded levels, "
-                               f"alpha=1.5, gamma=0.4, r=4, seeded kappa(x,t) and f(x,t)",
-                   "n": pb.n, "M": M, "solver": args.solver, "precision": args.precision,
-                   "krylov_tol": params.krylov_tol, "soe_tol": params.soe_tol, "nexp": nexp,
-                   "avg_iterations": float(np.mean(mv) / 2), "parallelism": "single GPU"},
+        "config": {"workload": f"1-D time-space fractional diffusion (IFL), n={pb.n} interior nodes, "
+                               f"M={pb.M} graded levels, alpha=1.5, gamma=0.4, r=4, seeded kappa(x,t), f(x,t)",
+                   "n": pb.n, "M": pb.M, "form": head["label"], "krylov_tol": args.tol, "soe_tol": 1e-10,
+                   "nexp": nexp, "avg_iterations": head["avg_iters"], "parallelism": "single GPU"},
+        "forms": {f: {k: v for k, v in r.items()} for f, r in res.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_levels", "kernel_ms_per_launch": kern_ms,
-                     "bytes_per_launch": bytes_launch},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_levels",
+                     "kernel_ms_per_launch": head["kernel_ms"], "bytes_per_launch": head["bytes"]},
     }
+    if "plain" in res:
+        out["speedup_vs_plain_fp64"] = head["value"] / res["plain"]["value"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args)
-    prob.close()
     print(json.dumps(out))
 
 
