@@ -94,11 +94,17 @@ typedef struct fids_params {
     int32_t precond;      /* FIDS_STRANG | FIDS_NONE                               */
     int32_t kappa_time_dependent; /* 1: kappa_d is [M][n]; 0: kappa_d is [n]      */
     int32_t x0_mode;      /* 0: zero initial guess (Sec. 5); 1: u^{m-1}            */
-    int32_t store_states; /* 1: keep every u^m in the workspace (needed by        */
-                          /* fids_adjoint); 0: keep only what stepping needs       */
+    int32_t store_states; /* 1: keep every u^m in the workspace (fids_adjoint     */
+                          /* then needs no recomputation); 0: keep only what       */
+                          /* stepping needs                                        */
     int32_t wg_count;     /* workgroups that cooperate on one problem; 0 = auto    */
     int32_t soe_helpers;  /* workgroups that stream the SOE history one level      */
                           /* ahead of the solve: -1 auto, 0 none, k > 0 exactly k  */
+                          /* (ignored, i.e. 0, when checkpoint_every > 0)          */
+    int32_t checkpoint_every; /* C > 0: the forward run snapshots its state (u^{m-1},*/
+                          /* u^{m-2}, the SOE history F^{(m-1)}) at levels         */
+                          /* m = kC + 1 and fids_adjoint recomputes each segment   */
+                          /* of C levels from its snapshot; 0: no snapshots        */
 } fids_params;
 
 /* Per-level report. */
@@ -116,7 +122,7 @@ typedef struct fids_problem fids_problem;
 /* Fills *p with: alpha 1.5, gamma 0.5, l 1, T 1, n 255, M 64, r 3, mu 0,
  * soe_tol 1e-10, krylov_tol 1e-12, krylov_maxit 200, restart 20, BiCGSTAB,
  * FP64, Strang, kappa_time_dependent 1, x0_mode 0, store_states 0, wg_count 0,
- * soe_helpers -1. */
+ * soe_helpers -1, checkpoint_every 0. */
 int fids_params_default(fids_params* p);
 
 /* Bytes of device workspace the problem needs (256-byte multiple).
@@ -146,12 +152,28 @@ int fids_step(fids_problem* h, double* u_out_d, fids_step_info* info);
  * the levels advanced by this call (index m-1). */
 int fids_solve_all(fids_problem* h, double* uT_d, double* u_all_d, fids_step_info* per_step);
 
-/* Exact discrete adjoint of the FIDS steps run since the last reset, for a
- * loss J(u^M): given dJ/du^M it returns dJ/dkappa (shape of kappa_d),
- * dJ/df ([M][n]) and dJ/dphi ([n]); any output may be NULL.  Needs
- * store_states = 1 and a completed forward run to level M (else FIDS_ESTATE). */
+/* Exact discrete adjoint of the FIDS steps (eq. 3.16gu with the SOE history
+ * recurrence of Lemma 2.2 / eq. 2.9), for a loss J(u^M): given dJ/du^M
+ * (dJ_duT_d, [n]) it returns dJ/dkappa (shape of kappa_d: [M][n] or [n]),
+ * dJ/df ([M][n], row m-1 for f^m) and dJ/dphi ([n]); any output may be NULL.
+ * Backward over m = M..1 it solves the transposed systems
+ *     (b_m' I + A K_m) lambda^m = ubar^m,   computed as   lambda^m = K_m^{-1} y,
+ *     (b_m' I + K_m A) y = K_m ubar^m       (the same preconditioned solver),
+ * runs the history recurrence in reverse (one adjoint history array of the
+ * forward's size) and accumulates dJ/dkappa^m_i = -lambda^m_i (A u^m)_i,
+ * dJ/df^m = lambda^m, dJ/dphi = ubar^0.  Needs a completed forward run to
+ * level M and either store_states = 1 (forward states read back, the forward
+ * state stays at level M) or checkpoint_every > 0 (each segment is recomputed
+ * from its snapshot; afterwards the forward state is at level
+ * min(checkpoint_every, M), and fids_solve_all advances it to M again), else
+ * FIDS_ESTATE.  FIDS_ENOCONV / FIDS_ENUMERIC if a transposed solve fails
+ * (the outputs are then incomplete).  Synchronous. */
 int fids_adjoint(fids_problem* h, const double* dJ_duT_d, double* g_kappa_d,
                  double* g_f_d, double* g_phi_d);
+
+/* Host copy of the per-level reports of the last fids_adjoint's transposed
+ * solves (M entries, index m-1; relres relative to ||K_m ubar^m||). */
+int fids_adjoint_report(const fids_problem* h, fids_step_info* per_step);
 
 /* Back to level 0 (u^0 = phi, empty history).  Set-up tables are kept; the
  * per-level preconditioner symbols are marked stale, so the next step or

@@ -82,6 +82,10 @@ struct Layout {
   size_t qhat, qhatf;
   size_t Tb, q, Tq;
   size_t u[3], F, kap, vec[10], uhist, T, Tf, tau, V, Z, soec, H1, AU, sync2, hflag;
+  // adjoint: segment snapshots and the adjoint descriptor's state
+  size_t ckpt, aprob, ainfo, astatus, ubar[3], yr[3], Fbar, alam, gk, AUa;
+  int nck;          // snapshots held (levels kC + 1, k = 1..nck)
+  int hist_cap;     // states uhist holds
   size_t total;
   int chunk;
   int twshift;
@@ -144,7 +148,22 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   lo.H1 = take(2 * L * 8);
   lo.AU = take(2 * L * 8);
   for (int i = 0; i < 10; ++i) lo.vec[i] = take(L * 8);
-  lo.uhist = p.store_states ? take((M + 1) * L * 8) : 0;
+  const size_t C = size_t(std::max(p.checkpoint_every, 0));
+  lo.hist_cap = p.store_states ? int(M + 1) : (C > 0 ? int(std::min(C, M) + 1) : 0);
+  lo.uhist = lo.hist_cap ? take(size_t(lo.hist_cap) * L * 8) : 0;
+  lo.nck = (!p.store_states && C > 0) ? int((M - 1) / C) : 0;
+  lo.ckpt = lo.nck ? take(size_t(lo.nck) * (ne + 4) * L * 8) : 0;
+  if (p.store_states || C > 0) {
+    lo.aprob = take(sizeof(Prob));
+    lo.ainfo = take(M * sizeof(fids_step_info));
+    lo.astatus = take(4 * sizeof(int));
+    for (int i = 0; i < 3; ++i) lo.ubar[i] = take(L * 8);
+    for (int i = 0; i < 3; ++i) lo.yr[i] = take(L * 8);
+    lo.Fbar = take(ne * L * 8);
+    lo.alam = take(L * 8);
+    lo.gk = take(L * 8);
+    lo.AUa = take(2 * L * 8);
+  }
   const bool gm = p.solver == FIDS_FGMRES;
   lo.V = gm ? take(size_t(p.restart + 1) * L * 8) : 0;
   lo.Z = gm ? take(size_t(p.restart) * L * (mixed ? 4 : 8)) : 0;
@@ -213,6 +232,8 @@ struct fids_problem {
   char* ws = nullptr;
   Prob hp{};
   Prob* dp = nullptr;
+  Prob ha{};                 // adjoint descriptor (when the layout has one)
+  Prob* dpa = nullptr;
   SymJob hj{};
   SymJob* dj = nullptr;
   int* dabort = nullptr;
@@ -268,17 +289,33 @@ int ensure_symbols(fids_problem* h) {
   return FIDS_OK;
 }
 
+// One cooperative launch of the level kernel for descriptor `d` and a wait
+// for its status words {status, last completed level}.
+int launch_wait(fids_problem* h, const Prob& hd, Prob* d, int m_begin, int m_end, int hist_lo, int ckpt_on,
+                int stat[2]) {
+  HIPCHK(hipMemsetAsync(h->dabort, 0, sizeof(int), h->stream));
+  HIPCHK(fids::launch_levels(d, 1, hd.ng + hd.nh, h->lds, m_begin, m_end, hist_lo, ckpt_on, h->timeout_ticks,
+                             h->dabort, h->stream));
+  HIPCHK(hipMemcpyAsync(stat, hd.status, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (stat[0] == FIDS_EDEVICE) {
+    // a group barrier timed out: clear the barrier words for the next launch
+    HIPCHK(hipMemsetAsync(hd.bar, 0, 4 * sizeof(unsigned), h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  return FIDS_OK;
+}
+
+int hist_lo_of(const fids_problem* h) { return h->prm.store_states ? 0 : -1; }
+
 int run_levels(fids_problem* h, int64_t m_end, fids_step_info* infos_host /*[M] indexed m-1*/) {
   if (h->level >= h->sh.M || h->poisoned) return FIDS_ESTATE;
   int st = ensure_symbols(h);
   if (st != FIDS_OK) return st;
   const int m_begin = int(h->level + 1);
-  HIPCHK(hipMemsetAsync(h->dabort, 0, sizeof(int), h->stream));
-  HIPCHK(fids::launch_levels(h->dp, 1, h->hp.ng + h->hp.nh, h->lds, m_begin, int(m_end), h->timeout_ticks,
-                             h->dabort, h->stream));
   int stat[2] = {0, 0};
-  HIPCHK(hipMemcpyAsync(stat, h->dstatus, sizeof(stat), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
+  st = launch_wait(h, h->hp, h->dp, m_begin, int(m_end), hist_lo_of(h), h->lo.nck > 0, stat);
+  if (st != FIDS_OK) return st;
   const int64_t last = stat[1];
   const int64_t first = m_begin;
   const int64_t upto = std::min<int64_t>(m_end, std::max<int64_t>(last + (stat[0] != FIDS_OK ? 1 : 0), first - 1));
@@ -288,12 +325,29 @@ int run_levels(fids_problem* h, int64_t m_end, fids_step_info* infos_host /*[M] 
   }
   if (last >= first) h->level = last;
   if (stat[0] != FIDS_OK) h->poisoned = true;
-  if (stat[0] == FIDS_EDEVICE) {
-    // a group barrier timed out: clear the barrier words for the next launch
-    HIPCHK(hipMemsetAsync(h->hp.bar, 0, 4 * sizeof(unsigned), h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-  }
   return stat[0];
+}
+
+// Forward state entering level a = kC + 1 from its snapshot (a = 1: the
+// initial state u^0 = u^{-1} = phi, empty history).
+int restore_segment(fids_problem* h, int a) {
+  const Prob& hp = h->hp;
+  const size_t vb = size_t(hp.vlen) * 8;
+  if (a == 1) {
+    HIPCHK(hipMemsetAsync(hp.F, 0, size_t(hp.nexp) * vb, h->stream));
+    HIPCHK(hipMemsetAsync(hp.AU, 0, 2 * vb, h->stream));
+    HIPCHK(fids::launch_init_state(hp, h->dp, h->stream));
+    return FIDS_OK;
+  }
+  const int C = hp.ckpt_every;
+  const double* ck = hp.ckpt + size_t((a - 1) / C - 1) * size_t(hp.nexp + 4) * hp.vlen;
+  const size_t v = size_t(hp.vlen);
+  HIPCHK(hipMemcpyAsync(hp.u[(a - 1) % 3], ck, vb, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(hp.u[(a + 1) % 3], ck + v, vb, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(hp.AU + size_t((a - 1) & 1) * v, ck + 2 * v, vb, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(hp.AU + size_t(a & 1) * v, ck + 3 * v, vb, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(hp.F, ck + 4 * v, size_t(hp.nexp) * vb, hipMemcpyDeviceToDevice, h->stream));
+  return FIDS_OK;
 }
 
 }  // namespace
@@ -308,7 +362,7 @@ int fids_params_default(fids_params* p) {
   p->soe_tol = 1e-10; p->krylov_tol = 1e-12; p->krylov_maxit = 200; p->restart = 20;
   p->solver = FIDS_BICGSTAB; p->precision = FIDS_FP64; p->precond = FIDS_STRANG;
   p->kappa_time_dependent = 1; p->x0_mode = 0; p->store_states = 0; p->wg_count = 0;
-  p->soe_helpers = -1;
+  p->soe_helpers = -1; p->checkpoint_every = 0;
   return FIDS_OK;
 }
 
@@ -408,6 +462,9 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
   hp.zf = (lo.Z && mixed) ? at<float>(ws, lo.Z) : nullptr;
   hp.uhist = lo.uhist ? at<double>(ws, lo.uhist) : nullptr;
   hp.T = at<double2>(ws, lo.T); hp.Tf = at<float2>(ws, lo.Tf);
+  hp.ckpt_every = std::max(p->checkpoint_every, 0);
+  hp.ckpt = lo.ckpt ? at<double>(ws, lo.ckpt) : nullptr;
+  hp.adjoint = 0;
   hp.part = at<double>(ws, lo.part);
   hp.info = at<fids_step_info>(ws, lo.info);
   hp.status = at<int>(ws, lo.status);
@@ -442,7 +499,28 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
     // latency-bound solve more than it saved (976 -> 897 levels/s with 128)
     int nh = p->soe_helpers >= 0 ? p->soe_helpers : env_int("FIDS_HELPERS", 0);
     nh = std::max(0, std::min({nh, resident - hp.ng, 1024}));   // hflag holds 1024 lines
+    // snapshots are taken where the solver group streams the history itself
+    if (p->checkpoint_every > 0) nh = 0;
     hp.nh = nh;
+  }
+  if (lo.aprob) {
+    Prob& ha = h->ha;
+    ha = hp;
+    ha.adjoint = 1;
+    ha.nh = 0;
+    ha.f = nullptr;
+    ha.ckpt = nullptr;
+    for (int i = 0; i < 3; ++i) ha.u[i] = at<double>(ws, lo.yr[i]);
+    for (int i = 0; i < 3; ++i) ha.ubar[i] = at<double>(ws, lo.ubar[i]);
+    ha.F = at<double>(ws, lo.Fbar);
+    ha.lam = at<double>(ws, lo.alam);
+    ha.gk = at<double>(ws, lo.gk);
+    ha.AU = at<double>(ws, lo.AUa);
+    ha.info = at<fids_step_info>(ws, lo.ainfo);
+    ha.status = at<int>(ws, lo.astatus);
+    ha.g_kappa = nullptr;
+    ha.g_f = nullptr;
+    h->dpa = at<Prob>(ws, lo.aprob);
   }
   if (upload(h, lo.prob, &h->hp, sizeof(Prob)) != FIDS_OK) return fail(FIDS_EDEVICE);
   if (upload(h, lo.job, &h->hj, sizeof(SymJob)) != FIDS_OK) return fail(FIDS_EDEVICE);
@@ -515,9 +593,65 @@ int fids_solve_all(fids_problem* h, double* uT_d, double* u_all_d, fids_step_inf
   return FIDS_OK;
 }
 
-int fids_adjoint(fids_problem* h, const double*, double*, double*, double*) {
-  if (!h) return FIDS_EINVAL;
-  return FIDS_ESTATE;
+int fids_adjoint(fids_problem* h, const double* dJ_duT_d, double* g_kappa_d, double* g_f_d, double* g_phi_d) {
+  if (!h || !dJ_duT_d) return FIDS_EINVAL;
+  if (!h->dpa || h->poisoned || h->level != h->sh.M) return FIDS_ESTATE;
+  int st = ensure_symbols(h);
+  if (st != FIDS_OK) return st;
+  const int M = int(h->sh.M);
+  Prob& ha = h->ha;
+  const size_t vb = size_t(ha.vlen) * 8;
+  ha.g_kappa = (ha.kappa_td && g_kappa_d) ? g_kappa_d : nullptr;
+  ha.g_f = g_f_d;
+  HIPCHK(hipMemcpyAsync(h->dpa, &ha, sizeof(Prob), hipMemcpyHostToDevice, h->stream));
+  for (int i = 0; i < 3; ++i) {
+    HIPCHK(hipMemsetAsync(ha.ubar[i], 0, vb, h->stream));
+    HIPCHK(hipMemsetAsync(ha.u[i], 0, vb, h->stream));
+  }
+  HIPCHK(hipMemsetAsync(ha.F, 0, size_t(ha.nexp) * vb, h->stream));
+  HIPCHK(hipMemsetAsync(ha.gk, 0, vb, h->stream));
+  HIPCHK(hipMemsetAsync(ha.lam, 0, vb, h->stream));
+  HIPCHK(hipMemsetAsync(ha.status, 0, 4 * sizeof(int), h->stream));
+  HIPCHK(fids::launch_from_natural(ha, h->dpa, dJ_duT_d, ha.ubar[M % 3], h->stream));
+  int stat[2] = {0, 0};
+  if (h->prm.store_states) {
+    st = launch_wait(h, ha, h->dpa, M, 1, 0, 0, stat);
+    if (st != FIDS_OK) return st;
+    if (stat[0] != FIDS_OK) return stat[0];
+    if (stat[1] != 1) return FIDS_EDEVICE;
+  } else {
+    const int C = h->hp.ckpt_every;
+    const int nseg = (M + C - 1) / C;
+    for (int k = nseg - 1; k >= 0; --k) {
+      const int a = k * C + 1, b = std::min((k + 1) * C, M);
+      st = restore_segment(h, a);
+      if (st != FIDS_OK) return st;
+      int fst[2] = {0, 0};
+      HIPCHK(hipMemsetAsync(h->hp.status, 0, 2 * sizeof(int), h->stream));
+      st = launch_wait(h, h->hp, h->dp, a, b, a - 1, 0, fst);
+      if (st != FIDS_OK) return st;
+      h->level = fst[1];
+      if (fst[0] != FIDS_OK || fst[1] != b) {
+        h->poisoned = true;
+        return fst[0] != FIDS_OK ? fst[0] : FIDS_EDEVICE;
+      }
+      st = launch_wait(h, ha, h->dpa, b, a, a - 1, 0, stat);
+      if (st != FIDS_OK) return st;
+      if (stat[0] != FIDS_OK) return stat[0];
+      if (stat[1] != a) return FIDS_EDEVICE;
+    }
+  }
+  if (g_phi_d) HIPCHK(fids::launch_to_natural(ha, h->dpa, ha.ubar[0], g_phi_d, h->stream));
+  if (g_kappa_d && !ha.kappa_td) HIPCHK(fids::launch_to_natural(ha, h->dpa, ha.gk, g_kappa_d, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return FIDS_OK;
+}
+
+int fids_adjoint_report(const fids_problem* h, fids_step_info* per_step) {
+  if (!h || !per_step) return FIDS_EINVAL;
+  if (!h->dpa) return FIDS_ESTATE;
+  HIPCHK(hipMemcpy(per_step, h->ha.info, size_t(h->sh.M) * sizeof(fids_step_info), hipMemcpyDeviceToHost));
+  return FIDS_OK;
 }
 
 // ---------------------------------------------------------------- batched (not yet built)

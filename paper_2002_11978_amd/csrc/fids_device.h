@@ -84,6 +84,18 @@ struct Prob {
   double* AU;                   // [2][vlen] A u^m of the last two levels, slot m & 1
   unsigned* sync2;              // [0]: helper step completions, [64]: last completed level
   unsigned* hflag;              // [nh][64]: per-helper release flags (one 256-byte line each)
+  // forward snapshots for the adjoint's segment recomputation
+  int ckpt_every;               // C (0: none)
+  double* ckpt;                 // [(M-1)/C][nexp + 4][vlen]: u^{m-1}, u^{m-2}, A u^{m-1}, A u^{m-2}, F^{(m-1)}
+  // adjoint descriptor only (adjoint = 1): u[] holds the transposed solutions
+  // y^m (lambda^m = y^m / kappa^m), F the adjoint history, uhist the forward
+  // states u^m read back
+  int adjoint;
+  double* ubar[3];              // ubar^m lives in ubar[m % 3]
+  double* lam;                  // lambda of the last finished level, tile-major
+  double* gk;                   // dJ/dkappa accumulated over levels (time-independent kappa), tile-major
+  double* g_kappa;              // caller's [M][n] dJ/dkappa (time-dependent kappa) or null
+  double* g_f;                  // caller's [M][n] dJ/df or null
 };
 
 // Bluestein / symbol-precompute descriptor (batched over levels).

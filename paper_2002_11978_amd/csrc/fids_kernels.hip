@@ -493,6 +493,9 @@ struct Ctl {
   unsigned gen;
   unsigned long long timeout;
   int* abort_flag;
+  int hist_lo;     // >= 0: store u^k at uhist[k - hist_lo]; < 0: keep no states
+  int ckpt_on;     // forward: write the segment snapshots
+  int pending;     // adjoint: the kappa gradient of level m+1 waits in T
 };
 
 // FGMRES small state in LDS: hraw (J+1)J, R J*J, and 8 vectors of J+1.
@@ -642,7 +645,8 @@ __device__ __forceinline__ int helper_loop(const Prob& p, int hr, int k0, int k1
 //   warm: column pass of A on x0 (the residual follows after the row pass);
 //   cold: r0 = b (BiCGSTAB also r^ = p = b), column pass of P^{-1} on b.
 template <typename RP>
-__device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const Lds& L, bool fused) {
+__device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const Lds& L, bool fused,
+                                          const Ctl& ctl) {
   const Plan& pl = L.pl;
   const int nexp = p.nexp;
   const bool self_soe = p.nh == 0;
@@ -672,6 +676,10 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
   const double* Au1 = p.AU + size_t((m - 1) & 1) * p.vlen;
   double* Au2 = p.AU + size_t(m & 1) * p.vlen;   // A u^{m-2} in, A x0 out
   const int blk = 2 * pl.CT * pl.N1;
+  // snapshot of the state entering level m = kC + 1 (k >= 1), taken while it
+  // streams through this phase
+  const bool snap = ctl.ckpt_on && p.ckpt != nullptr && m >= 2 && (m - 1) % p.ckpt_every == 0;
+  double* ck = snap ? p.ckpt + size_t((m - 1) / p.ckpt_every - 1) * size_t(nexp + 4) * p.vlen : nullptr;
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
     double acc[2] = {0.0, 0.0};
@@ -686,11 +694,17 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
         double2 d = make_double2(0.0, 0.0);
         if (m >= 2) {
           const double2 a2 = ld2(um2, off);
+          if (snap) {
+            st2(ck, off, a1);
+            st2(ck + p.vlen, off, a2);
+          }
           d = make_double2(a1.x - a2.x, a1.y - a2.y);
           if (self_soe) {
             double* Fp = p.F + size_t(tile) * nexp * blk + 2 * idx;
+            double* Fc = snap ? ck + size_t(4) * p.vlen + size_t(tile) * nexp * blk + 2 * idx : nullptr;
             for (int j = 0; j < nexp; ++j) {
               double2 fj = ld2(Fp, j * blk);
+              if (snap) st2(Fc, j * blk, fj);
               fj.x = de[j] * fj.x + th[j] * d.x;
               fj.y = de[j] * fj.y + th[j] * d.y;
               st2(Fp, j * blk, fj);
@@ -712,12 +726,16 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
         if (warm) x0 = mask2(make_double2(a1.x + rho * d.x, a1.y + rho * d.y), i0, p.n);
         if (fused) {
           const double2 A1 = ld2(Au1, off), A2 = ld2(Au2, off);
+          if (snap) {
+            st2(ck + 2 * size_t(p.vlen), off, A1);
+            st2(ck + 3 * size_t(p.vlen), off, A2);
+          }
           const double2 ax = make_double2((1.0 + rho) * A1.x - rho * A2.x, (1.0 + rho) * A1.y - rho * A2.y);
           st2(Au2, off, mask2(ax, i0, p.n));
           r0 = mask2(make_double2(b.x - (bm * x0.x + kk.x * ax.x), b.y - (bm * x0.y + kk.y * ax.y)), i0, p.n);
         }
         st2(p.kap, off, kk);
-        if (p.store_states) st2(p.uhist + size_t(m - 1) * p.vlen, off, a1);
+        if (ctl.hist_lo >= 0) st2(p.uhist + size_t(m - 1 - ctl.hist_lo) * p.vlen, off, a1);
       }
       st2(p.vec[VB], off, b);
       st2(x, off, x0);
@@ -782,6 +800,170 @@ __device__ __forceinline__ void phase_r0(const Prob& p, int m, int rank, const L
     const int sl_rr[1] = {SL_RR};
     write_partials<1>(p, tile, sl_rr, acc);
     tileA_fft_store<RP>(pl, tile, lbuf<RP>(L), pT<RP>(p));
+  }
+}
+
+// ------------------------------------------------------------- adjoint
+// The transposed system of level m, (b_m' I + A K_m) lambda = ubar^m, equals
+// K_m^{-1} (b_m' I + K_m A) K_m lambda = ubar^m, so it is solved as the forward
+// system with right-hand side K_m ubar^m: y = (b_m' I + K_m A)^{-1} K_m ubar^m,
+// lambda^m = y / kappa^m, with the forward preconditioner and solver.
+
+// Finishes dJ/dkappa^{m+1} = -lambda^{m+1} .* A u^{m+1} from the buffer the
+// column pass C just left (A u^{m+1} scaled by Nc): a row of the caller's
+// [M][n] array for time-dependent kappa, else the tile-major running sum.
+__device__ __forceinline__ void adj_grad_item(const Prob& p, int mg, int i0, int off, double2 y) {
+  const double2 lm = ld2(p.lam, off);
+  const double2 g = make_double2(-lm.x * y.x, -lm.y * y.y);
+  if (p.kappa_td) {
+    if (p.g_kappa) {
+      double* row = p.g_kappa + size_t(mg - 1) * p.n;
+      row[i0] = g.x;
+      if (i0 + 1 < p.n) row[i0 + 1] = g.y;
+    }
+  } else {
+    const double2 a = ld2(p.gk, off);
+    st2(p.gk, off, mask2(make_double2(a.x + g.x, a.y + g.y), i0, p.n));
+  }
+}
+
+// Right-hand side of adjoint level m: b = kappa^m .* ubar^m, initial guess 0 or
+// the extrapolation y^{m+1} + rho (y^{m+1} - y^{m+2}), rho = tau_{m+1}/tau_{m+2};
+// then the column pass of A on x0 (warm) or of P^{-1} on b (cold).  First the
+// pending gradient of level m+1 (column pass C of A u^{m+1}).
+template <typename RP>
+__device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, const Lds& L, const Ctl& ctl) {
+  const Plan& pl = L.pl;
+  const double inv = 1.0 / double(pl.Nc);
+  const bool warm = p.x0_mode != 0;
+  const bool bicg = p.solver == FIDS_BICGSTAB;
+  const double* ub = p.ubar[m % 3];
+  const double* y1 = p.u[(m + 1) % 3];
+  const double* y2 = p.u[(m + 2) % 3];
+  double* x = p.u[m % 3];
+  const double rho = (m + 2 <= p.M) ? p.tau[m + 1] / p.tau[m + 2] : 0.0;
+  const double* km = p.kappa + (p.kappa_td ? size_t(m - 1) * p.n : 0);
+  for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
+    const TileIdx t = tile_idx(pl, tile);
+    if (ctl.pending) tileC_load_ifft<double>(pl, tile, p.T, L.bd);
+    double acc[1] = {0.0};
+    for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
+      int i0, sl;
+      item(pl, t, idx, i0, sl);
+      const int off = t.toff + 2 * idx;
+      double2 b = make_double2(0.0, 0.0), x0 = make_double2(0.0, 0.0);
+      if (i0 < p.n) {
+        if (ctl.pending) adj_grad_item(p, m + 1, i0, off, cscale<double>(L.bd[sl], inv));
+        const double2 kk = nat2(km, i0, p.n);
+        const double2 u = ld2(ub, off);
+        b = mask2(make_double2(kk.x * u.x, kk.y * u.y), i0, p.n);
+        if (warm) {
+          const double2 a1 = ld2(y1, off), a2 = ld2(y2, off);
+          x0 = mask2(make_double2(a1.x + rho * (a1.x - a2.x), a1.y + rho * (a1.y - a2.y)), i0, p.n);
+        }
+        st2(p.kap, off, kk);
+      }
+      st2(p.vec[VB], off, b);
+      st2(x, off, x0);
+      acc[0] += b.x * b.x + b.y * b.y;
+      if (warm) {
+        L.bd[sl] = x0;
+      } else {
+        st2(p.vec[VR], off, b);
+        if (bicg) { st2(p.vec[VRH], off, b); st2(p.vec[VP], off, b); }
+        lbuf<RP>(L)[sl] = tocx<RP>(b);
+      }
+    }
+    const int sls[1] = {SL_BB};
+    write_partials<1>(p, tile, sls, acc);
+    if (warm) tileA_fft_store<double>(pl, tile, L.bd, p.T);
+    else tileA_fft_store<RP>(pl, tile, lbuf<RP>(L), pT<RP>(p));
+  }
+}
+
+// After the solve of adjoint level m (y^m in u[m % 3]):
+//   lambda = y / kappa^m;  dJ/df^m = lambda;  ubar^{m-1} += b_m' lambda;
+// the history recurrence in reverse (m >= 2; F^{(1)} = 0 has no inputs):
+//   Fbar_j -= g w_j lambda;  rho = sum_j theta_{m,j} Fbar_j;  Fbar_j *= e^{-s_j tau_m};
+//   ubar^{m-1} += rho;  ubar^{m-2} = -rho  (its first contribution);
+// then the column pass of A on the forward state u^m.
+__device__ __forceinline__ void phase_adj_post(const Prob& p, int m, int rank, const Lds& L, const Ctl& ctl) {
+  const Plan& pl = L.pl;
+  const int nexp = p.nexp;
+  double* th = L.tab;
+  double* de = L.tab + nexp;
+  double* gw = L.tab + 2 * nexp;
+  __syncthreads();
+  for (int j = threadIdx.x; j < nexp; j += kThreads) {
+    th[j] = p.theta[size_t(m) * nexp + j];
+    de[j] = p.decay[size_t(m) * nexp + j];
+    gw[j] = p.gw[j];
+  }
+  __syncthreads();
+  const double bm = p.beta[m];
+  const double* y = p.u[m % 3];
+  double* u1 = p.ubar[(m - 1) % 3];
+  double* u2 = p.ubar[(m + 1) % 3];   // (m-2) mod 3
+  const double* um = p.uhist + size_t(m - ctl.hist_lo) * p.vlen;
+  double* gf = p.g_f ? p.g_f + size_t(m - 1) * p.n : nullptr;
+  const int blk = 2 * pl.CT * pl.N1;
+  for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
+    const TileIdx t = tile_idx(pl, tile);
+    for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
+      int i0, sl;
+      item(pl, t, idx, i0, sl);
+      const int off = t.toff + 2 * idx;
+      double2 uv = make_double2(0.0, 0.0);
+      if (i0 < p.n) {
+        const double2 yy = ld2(y, off), kk = ld2(p.kap, off);
+        const double2 lm = make_double2(yy.x / kk.x, i0 + 1 < p.n ? yy.y / kk.y : 0.0);
+        st2(p.lam, off, lm);
+        if (gf) {
+          gf[i0] = lm.x;
+          if (i0 + 1 < p.n) gf[i0 + 1] = lm.y;
+        }
+        double2 a = ld2(u1, off);
+        a.x += bm * lm.x;
+        a.y += bm * lm.y;
+        if (m >= 2) {
+          double* Fp = p.F + size_t(tile) * nexp * blk + 2 * idx;
+          double2 r = make_double2(0.0, 0.0);
+          for (int j = 0; j < nexp; ++j) {
+            double2 fb = ld2(Fp, j * blk);
+            fb.x -= gw[j] * lm.x;
+            fb.y -= gw[j] * lm.y;
+            r.x += th[j] * fb.x;
+            r.y += th[j] * fb.y;
+            fb.x *= de[j];
+            fb.y *= de[j];
+            st2(Fp, j * blk, fb);
+          }
+          a.x += r.x;
+          a.y += r.y;
+          st2(u2, off, mask2(make_double2(-r.x, -r.y), i0, p.n));
+        }
+        st2(u1, off, mask2(a, i0, p.n));
+        uv = mask2(ld2(um, off), i0, p.n);
+      }
+      L.bd[sl] = uv;
+    }
+    tileA_fft_store<double>(pl, tile, L.bd, p.T);
+  }
+}
+
+// Column pass C of A u^m after the last level of an adjoint launch: the
+// gradient of that level (no level follows in this launch to absorb it).
+__device__ __forceinline__ void phase_adj_flush(const Prob& p, int m, int rank, const Lds& L) {
+  const Plan& pl = L.pl;
+  const double inv = 1.0 / double(pl.Nc);
+  for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
+    const TileIdx t = tile_idx(pl, tile);
+    tileC_load_ifft<double>(pl, tile, p.T, L.bd);
+    for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
+      int i0, sl;
+      item(pl, t, idx, i0, sl);
+      if (i0 < p.n) adj_grad_item(p, m, i0, t.toff + 2 * idx, cscale<double>(L.bd[sl], inv));
+    }
   }
 }
 
@@ -934,9 +1116,15 @@ __device__ __forceinline__ int level_start(const Prob& p, int m, int rank, Ctl& 
                                            double& bb, double& rr0) {
   // the helpers' history sum H1^m (step m-1) must be complete
   if (p.nh > 0 && m >= 3 && !wait_ge<8>(p, &p.sync2[0], unsigned(m - 2) * unsigned(p.nh), ctl)) return FIDS_EDEVICE;
-  const bool fused = p.solver == FIDS_FGMRES && p.x0_mode != 0 && m >= 3;
-  if (fp32pc) phase_rhs<float>(p, m, rank, L, fused);
-  else phase_rhs<double>(p, m, rank, L, fused);
+  const bool fused = p.solver == FIDS_FGMRES && p.x0_mode != 0 && m >= 3 && !p.adjoint;
+  if (p.adjoint) {
+    if (fp32pc) phase_adj_rhs<float>(p, m, rank, L, ctl);
+    else phase_adj_rhs<double>(p, m, rank, L, ctl);
+  } else if (fp32pc) {
+    phase_rhs<float>(p, m, rank, L, fused, ctl);
+  } else {
+    phase_rhs<double>(p, m, rank, L, fused, ctl);
+  }
   BARRIER();
   double red2[2];
   {
@@ -1407,8 +1595,27 @@ __device__ __forceinline__ int level_fgmres(const Prob& p, int m, int rank, Ctl&
 }
 
 // ------------------------------------------------------------- level kernel
+// Adjoint level m: transposed solve, reversed history step, A u^m for the
+// kappa gradient (finished by the next level's right-hand side phase or by
+// the flush after the launch's last level).
+__device__ __forceinline__ int level_adjoint(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L) {
+  int st;
+  if (p.solver == FIDS_BICGSTAB) st = level_bicgstab(p, m, rank, ctl, L);
+  else if (p.precision == FIDS_MIXED) st = level_fgmres<float>(p, m, rank, ctl, L);
+  else st = level_fgmres<double>(p, m, rank, ctl, L);
+  if (st != FIDS_OK) return st;
+  phase_adj_post(p, m, rank, L, ctl);
+  BARRIER();
+  phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd, L);
+  BARRIER();
+  return FIDS_OK;
+}
+
+// Persistent level kernel.  Forward descriptors advance m = m_begin..m_end;
+// adjoint descriptors run m = m_begin down to m_end (m_begin >= m_end).
 __global__ void __launch_bounds__(kThreads) k_levels(const Prob* probs, int nprob, int m_begin, int m_end,
-                                                     unsigned long long timeout, int* abort_flag) {
+                                                     int hist_lo, int ckpt_on, unsigned long long timeout,
+                                                     int* abort_flag) {
   extern __shared__ double2 dyn[];
   int pid = 0;
   for (int q = 0; q < nprob; ++q)
@@ -1457,7 +1664,22 @@ __global__ void __launch_bounds__(kThreads) k_levels(const Prob* probs, int npro
   ctl.gen = 0;
   ctl.timeout = timeout;
   ctl.abort_flag = abort_flag;
+  ctl.hist_lo = hist_lo;
+  ctl.ckpt_on = ckpt_on;
+  ctl.pending = 0;
   if (threadIdx.x == 0) ctl.gen = __hip_atomic_load(&p.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (p.adjoint) {
+    for (int m = m_begin; m >= m_end; --m) {
+      ctl.pending = m < m_begin;
+      const int st = level_adjoint(p, m, rank, ctl, L);
+      if (st != FIDS_OK) {
+        if (rank == 0 && threadIdx.x == 0 && st == FIDS_EDEVICE) p.status[0] = FIDS_EDEVICE;
+        return;
+      }
+    }
+    phase_adj_flush(p, m_end, rank, L);
+    return;
+  }
   if (rank >= p.ng) {                         // SOE helper
     helper_loop(p, rank - p.ng, max(2, m_begin - 1), m_end - 1, ctl, L.tab);
     return;
@@ -1480,14 +1702,15 @@ __global__ void __launch_bounds__(kThreads) k_levels(const Prob* probs, int npro
       __hip_atomic_store(&p.sync2[64], unsigned(m), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
-  // keep u^M with the stored states (tile-local copy, no barrier needed)
-  if (p.store_states && m_end == p.M) {
-    const double* uM = p.u[p.M % 3];
+  // keep u^{m_end} with the stored states (tile-local copy, no barrier needed)
+  if (hist_lo >= 0) {
+    const double* ue = p.u[m_end % 3];
+    double* dst = p.uhist + size_t(m_end - hist_lo) * p.vlen;
     for (int tile = rank; tile < L.pl.ntiles; tile += p.ng) {
       const TileIdx t = tile_idx(L.pl, tile);
       for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
         const int off = t.toff + 2 * idx;
-        st2(p.uhist + size_t(p.M) * p.vlen, off, ld2(uM, off));
+        st2(dst, off, ld2(ue, off));
       }
     }
   }
@@ -1521,6 +1744,18 @@ __global__ void __launch_bounds__(kThreads) k_to_natural(const Prob* pp, const d
     const double2 v = ld2(src, t.toff + 2 * idx);
     if (i0 < p.n) dst[i0] = v.x;
     if (i0 + 1 < p.n) dst[i0 + 1] = v.y;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_from_natural(const Prob* pp, const double* src, double* dst) {
+  const Prob& p = *pp;
+  const Plan& pl = p.pl;
+  const int tile = blockIdx.x;
+  const TileIdx t = tile_idx(pl, tile);
+  for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
+    int i0, sl;
+    item(pl, t, idx, i0, sl);
+    st2(dst, t.toff + 2 * idx, nat2(src, i0, p.n));
   }
 }
 
@@ -1648,6 +1883,11 @@ hipError_t launch_to_natural(const Prob& h, const Prob* d, const double* src, do
   return hipGetLastError();
 }
 
+hipError_t launch_from_natural(const Prob& h, const Prob* d, const double* src, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_from_natural, dim3(h.pl.ntiles), dim3(kThreads), 0, s, d, src, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_kbar(const double* kappa, int n, int M, int td, double* kbar, hipStream_t s) {
   hipLaunchKernelGGL(k_kbar, dim3(M), dim3(kThreads), 0, s, kappa, n, td, kbar);
   return hipGetLastError();
@@ -1683,9 +1923,10 @@ hipError_t set_level_lds_limit(size_t bytes) {
 }
 
 hipError_t launch_levels(const Prob* probs, int nprob, int total_wg, size_t lds_bytes, int m_begin,
-                         int m_end, unsigned long long timeout_ticks, int* abort_flag, hipStream_t s) {
-  void* args[] = {(void*)&probs, (void*)&nprob, (void*)&m_begin, (void*)&m_end, (void*)&timeout_ticks,
-                  (void*)&abort_flag};
+                         int m_end, int hist_lo, int ckpt_on, unsigned long long timeout_ticks, int* abort_flag,
+                         hipStream_t s) {
+  void* args[] = {(void*)&probs, (void*)&nprob, (void*)&m_begin, (void*)&m_end, (void*)&hist_lo,
+                  (void*)&ckpt_on, (void*)&timeout_ticks, (void*)&abort_flag};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_levels), dim3(total_wg), dim3(kThreads),
                                     args, static_cast<unsigned int>(lds_bytes), s);
 }

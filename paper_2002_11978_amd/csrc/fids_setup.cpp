@@ -27,6 +27,7 @@ int validate(const fids_params& p) {
   if (p.x0_mode != 0 && p.x0_mode != 1) return FIDS_EINVAL;
   if (p.wg_count < 0 || p.wg_count > 4096) return FIDS_EINVAL;
   if (p.soe_helpers < -1 || p.soe_helpers > 4096) return FIDS_EINVAL;
+  if (p.checkpoint_every < 0) return FIDS_EINVAL;
   if (p.n > (int64_t(1) << 21) || p.M > (int64_t(1) << 24)) return FIDS_EINVAL;
   return FIDS_OK;
 }

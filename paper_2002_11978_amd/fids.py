@@ -32,7 +32,7 @@ class Params(ctypes.Structure):
         ("restart", ctypes.c_int32), ("solver", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("precond", ctypes.c_int32), ("kappa_time_dependent", ctypes.c_int32),
         ("x0_mode", ctypes.c_int32), ("store_states", ctypes.c_int32), ("wg_count", ctypes.c_int32),
-        ("soe_helpers", ctypes.c_int32),
+        ("soe_helpers", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
     ]
 
 
@@ -59,6 +59,7 @@ _SIGS = {
     "fids_step": (ctypes.c_int, [_P, _P, ctypes.POINTER(StepInfo)]),
     "fids_solve_all": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(StepInfo)]),
     "fids_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "fids_adjoint_report": (ctypes.c_int, [_P, ctypes.POINTER(StepInfo)]),
     "fids_reset": (ctypes.c_int, [_P]),
     "fids_prepare": (ctypes.c_int, [_P]),
     "fids_destroy": (ctypes.c_int, [_P]),
@@ -232,9 +233,30 @@ class Problem:
         """Like solve_all with caller-provided outputs (no allocation)."""
         return lib().fids_solve_all(self.h, _ptr(uT), _ptr(uall), infos)
 
-    def adjoint(self, dJ_duT, g_kappa=None, g_f=None, g_phi=None):
+    def adjoint(self, dJ_duT, g_kappa=None, g_f=None, g_phi=None, allocate=True):
+        """dJ/dkappa, dJ/df, dJ/dphi for a loss J(u^M) with gradient dJ_duT.
+
+        Outputs left as None are allocated when `allocate` is true, else
+        not computed.
+        """
+        torch = self.torch
+        if allocate:
+            if g_kappa is None:
+                g_kappa = torch.empty_like(self.kappa)
+            if g_f is None:
+                g_f = torch.empty((self.M, self.n), dtype=torch.float64, device=self.device)
+            if g_phi is None:
+                g_phi = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        for name, t in (("dJ_duT", dJ_duT), ("g_kappa", g_kappa), ("g_f", g_f), ("g_phi", g_phi)):
+            if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 device tensor")
         _check(lib().fids_adjoint(self.h, _ptr(dJ_duT), _ptr(g_kappa), _ptr(g_f), _ptr(g_phi)), "fids_adjoint")
         return g_kappa, g_f, g_phi
+
+    def adjoint_reports(self):
+        infos = (StepInfo * self.M)()
+        _check(lib().fids_adjoint_report(self.h, infos), "fids_adjoint_report")
+        return [LevelReport(i.m, i.iters, i.matvecs, i.relres) for i in infos]
 
     def reset(self):
         _check(lib().fids_reset(self.h), "fids_reset")
