@@ -20,6 +20,13 @@ the relative difference of their u(T) from the headline's.
 Extra JSON fields:
   roofline      algorithmic HBM bytes of the level kernel / its measured time
   cpu_baseline  the CPU oracle (direct scheme, dense LU) on a bounded sample
+  adjoint       adj/fwd wall-time ratio of the discrete adjoint at n = 16383,
+                M = 1024 (alpha 1.6, gamma 0.5, r 3, time-independent kappa),
+                snapshots every 32 levels (the adjoint recomputes each segment)
+                and with all states kept
+  batch         256 independent problems (n log-uniform in [511, 16383],
+                alpha ~ U(1.1, 1.9), gamma ~ U(0.2, 0.8), M = 256), one
+                workgroup each, all levels in one launch: problem-levels/s
 """
 from __future__ import annotations
 
@@ -53,6 +60,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-levels", type=int, default=24)
     ap.add_argument("--cpu-n", type=int, default=4095)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=256)
     return ap.parse_args()
 
 
@@ -111,6 +121,90 @@ def cpu_baseline(args):
     return {"value": K / dt, "unit": "levels/s", "cores": cores, "kind": "oracle",
             "sample": f"direct scheme + LAPACK dense LU (all host threads), first {K} of M={pb.M} levels of the "
                       f"same recipe at n={pb.n}; a dense LU at n=65535 does not fit a bounded run; {dt:.1f} s"}
+
+
+def adjoint_leg(tol):
+    """Forward solve and discrete adjoint of J = ||u^M||^2 at n = 16383, M = 1024."""
+    import torch
+
+    from paper_2002_11978_amd import fids
+    from paper_2002_11978_amd import workloads as W
+    pb = W.seeded(1.6, 0.5, 16383, 1024, r=3.0, kappa_seed=5, f_seed=7, time_dependent=False)
+    dev = torch.device("cuda:0")
+    k, f, phi = (torch.from_numpy(a).to(dev) for a in (pb.kappa, pb.f, pb.phi))
+    out = {"workload": "n=16383, M=1024, alpha=1.6, gamma=0.5, r=3, time-independent kappa (seed 5), f seed 7",
+           "form": FORMS["headline"]["label"]}
+    for name, extra in (("checkpoint_32", dict(checkpoint_every=32)), ("stored_states", dict(store_states=1))):
+        prm = fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=pb.M, r=pb.r, soe_tol=1e-10,
+                                  krylov_tol=tol, krylov_maxit=500, kappa_time_dependent=0, solver=1, x0_mode=1,
+                                  **extra)
+        prob = fids.Problem(prm, k, f, phi)
+        best = None
+        for _ in range(2):
+            prob.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            uT, _, _ = prob.solve_all()
+            torch.cuda.synchronize()
+            tf = time.perf_counter() - t0
+            dJ = (2.0 * uT).contiguous()
+            t0 = time.perf_counter()
+            prob.adjoint(dJ)
+            torch.cuda.synchronize()
+            ta = time.perf_counter() - t0
+            if best is None or tf + ta < best[0] + best[1]:
+                best = (tf, ta)
+        reps = prob.adjoint_reports()
+        out[name] = {"fwd_ms": best[0] * 1e3, "adj_ms": best[1] * 1e3, "adj_over_fwd": best[1] / best[0],
+                     "adj_avg_iters": float(np.mean([r.iters for r in reps]))}
+        print(f"[bench] adjoint {name}: fwd {best[0] * 1e3:.1f} ms, adjoint {best[1] * 1e3:.1f} ms, "
+              f"ratio {best[1] / best[0]:.2f}", file=sys.stderr, flush=True)
+        prob.close()
+    out["adj_over_fwd"] = out["checkpoint_32"]["adj_over_fwd"]
+    return out
+
+
+def batch_leg(tol, count):
+    """256 heterogeneous problems advanced together; problem-levels/s."""
+    import torch
+
+    from paper_2002_11978_amd import fids
+    from paper_2002_11978_amd import workloads as W
+    M = 256
+    pbs = [W.batch_member(p, M=M) for p in range(count)]
+    dev = torch.device("cuda:0")
+    arrs = [[torch.from_numpy(getattr(pb, a)).to(dev) for pb in pbs] for a in ("kappa", "f", "phi")]
+    out = {"workload": f"{count} problems, n log-uniform in [511, 16383] (sum {sum(pb.n for pb in pbs)}), "
+                       f"alpha~U(1.1,1.9), gamma~U(0.2,0.8), r=(2-gamma)/gamma, M={M}, seeded kappa(x,t), f(x,t)",
+           "count": count, "M": M}
+    for name, cfg in (("fp64", dict(solver=1, precision=0, x0_mode=1)),
+                      ("mixed", dict(solver=1, precision=1, x0_mode=1))):
+        params = [fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=M, r=pb.r, soe_tol=1e-10,
+                                      krylov_tol=tol, krylov_maxit=500, **cfg) for pb in pbs]
+        t0 = time.perf_counter()
+        b = fids.Batch(params, *arrs)
+        t_init = time.perf_counter() - t0
+        infos = (fids.StepInfo * (count * M))()
+        best = None
+        for _ in range(3):
+            b.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = b.solve_all_raw(None, infos)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if st != 0:
+                raise fids.FidsError(st, "fids_batch_solve_all")
+            best = dt if best is None else min(best, dt)
+        its = np.array([infos[i].iters for i in range(count * M)])
+        fb = np.array([infos[i].pc_fp64_iters for i in range(count * M)])
+        out[name] = {"problem_levels_per_s": count * M / best, "solve_ms": best * 1e3, "init_s": t_init,
+                     "avg_iters": float(its.mean()), "levels_with_fp64_pc": int((fb > 0).sum()),
+                     "form": f"fgmres(20)-{'fp64' if cfg['precision'] == 0 else 'fp64/fp32pc'}-x0extrap"}
+        print(f"[bench] batch {name}: {count * M / best:.0f} problem-levels/s ({best * 1e3:.1f} ms), "
+              f"its {its.mean():.2f}, fp64-pc levels {(fb > 0).sum()}", file=sys.stderr, flush=True)
+        b.close()
+    return out
 
 
 class Runner:
@@ -247,6 +341,11 @@ def main():
     }
     if "plain" in res:
         out["speedup_vs_plain_fp64"] = head["value"] / res["plain"]["value"]
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(args.tol)
+        out["adj_fwd_ratio"] = out["adjoint"]["adj_over_fwd"]
+    if not args.no_batch:
+        out["batch"] = batch_leg(args.tol, args.batch_count)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out))

@@ -64,7 +64,9 @@ extern "C" {
 #define FIDS_BICGSTAB 0   /* right-preconditioned BiCGSTAB (the paper's solver, Sec. 5) */
 #define FIDS_FGMRES   1   /* flexible GMRES(restart), right preconditioning          */
 #define FIDS_FP64     0   /* every FFT, vector and reduction in FP64                 */
-#define FIDS_MIXED    1   /* preconditioner FFTs in FP32, everything else FP64       */
+#define FIDS_MIXED    1   /* preconditioner FFTs in FP32, everything else FP64; a    */
+                          /* level unconverged after one restart cycle continues   */
+                          /* with the FP64 preconditioner                          */
 #define FIDS_STRANG   0   /* Strang circulant preconditioner, eq. (4.3)              */
 #define FIDS_NONE     1   /* no preconditioner (identity)                            */
 
@@ -115,6 +117,10 @@ typedef struct fids_step_info {
     int32_t matvecs;      /* applications of M^{(m)} (the paper's Its is           */
                           /* matvecs/2 for BiCGSTAB)                               */
     double  relres;       /* final ||b - M x|| / ||b|| as computed by the solver   */
+    int32_t pc_fp64_iters;/* FIDS_MIXED: iterations run with the FP64              */
+                          /* preconditioner after the first restart cycle missed   */
+                          /* the tolerance (0: the level finished in FP32)         */
+    int32_t reserved;
 } fids_step_info;
 
 typedef struct fids_problem fids_problem;
@@ -191,6 +197,10 @@ int fids_destroy(fids_problem* h);
 /* Static message for a status code. */
 const char* fids_strerror(int status);
 
+/* The call site and HIP message of the last failed HIP call made by the
+ * library in the calling thread ("" if none).  Valid until the next call. */
+const char* fids_last_error(void);
+
 /* ---------------- batched problems: independent instances of (1.1) -------- */
 typedef struct fids_batch fids_batch;
 
@@ -199,8 +209,11 @@ int fids_batch_workspace_size(const fids_params* p, int32_t count, size_t* bytes
 
 /* Like fids_init_problem for each problem i with its own parameters p[i] and
  * borrowed arrays kappa_d[i], f_d[i], phi_d[i] (host arrays of device
- * pointers).  All problems must share M (they advance level by level
- * together); n, alpha, gamma, r and the fields may differ. */
+ * pointers).  All problems must share M, solver and precision (FIDS_EINVAL
+ * otherwise); n, alpha, gamma, r, the tolerances, x0_mode, the
+ * preconditioner and the fields may differ.  Each member runs on one
+ * workgroup (store_states, checkpoint_every, soe_helpers and wg_count are
+ * ignored). */
 int fids_batch_init(const fids_params* p, int32_t count, const double* const* kappa_d,
                     const double* const* f_d, const double* const* phi_d, void* ws_d,
                     size_t ws_bytes, void* hip_stream, fids_batch** out);
@@ -213,6 +226,13 @@ int fids_batch_step(fids_batch* b, fids_step_info* info);
  * array [count][M]. */
 int fids_batch_solve_all(fids_batch* b, double* const* uT_d, fids_step_info* info);
 
+/* Per-member status after the last batch call: status[i] (FIDS_OK or the
+ * member's failure; a failed member stops while the others go on) and, if
+ * last_level is not NULL, the last level member i completed.  Host arrays of
+ * `count` entries. */
+int fids_batch_status(const fids_batch* b, int32_t* status, int64_t* last_level);
+
+/* Back to level 0 for every member (per-level symbols rebuilt on the next call). */
 int fids_batch_reset(fids_batch* b);
 int fids_batch_destroy(fids_batch* b);
 

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -81,7 +82,7 @@ struct Layout {
   size_t tw1r, tw1rf, tw2r, tw2rf, tw1c, tw1cf, tw2c, tw2cf, twlo, twlof, twhi, twhif;
   size_t qhat, qhatf;
   size_t Tb, q, Tq;
-  size_t u[3], F, kap, vec[10], uhist, T, Tf, tau, V, Z, soec, H1, AU, sync2, hflag;
+  size_t u[3], F, kap, vec[10], uhist, T, Tf, tau, V, Z, Zf, soec, H1, AU, sync2, hflag;
   // adjoint: segment snapshots and the adjoint descriptor's state
   size_t ckpt, aprob, ainfo, astatus, ubar[3], yr[3], Fbar, alam, gk, AUa;
   int nck;          // snapshots held (levels kC + 1, k = 1..nck)
@@ -89,6 +90,13 @@ struct Layout {
   size_t total;
   int chunk;
   int twshift;
+};
+
+// Batch workspace: descriptors, status words and level reports of all
+// members, then one single-problem workspace per member.
+struct BatchLayout {
+  size_t probs, status, info, head, total;
+  std::vector<size_t> member, member_bytes;
 };
 
 struct Shapes {
@@ -134,7 +142,8 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   lo.twlo = take(nlo * 16); lo.twlof = take(nlo * 8);
   lo.twhi = take(nhi * 16); lo.twhif = take(nhi * 8);
   const bool mixed = p.precision == FIDS_MIXED;
-  lo.qhat = mixed ? 0 : take((M + 1) * (Nc + 1) * 8);
+  // FP64 symbols always (the mixed form falls back to them), FP32 copies for the mixed form
+  lo.qhat = take((M + 1) * (Nc + 1) * 8);
   lo.qhatf = mixed ? take((M + 1) * (Nc + 1) * 4) : 0;
   // symbol scratch: about 64 MiB per chunk
   const size_t per = L * 16 + n * 8 + Nc * 16;
@@ -166,7 +175,8 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   }
   const bool gm = p.solver == FIDS_FGMRES;
   lo.V = gm ? take(size_t(p.restart + 1) * L * 8) : 0;
-  lo.Z = gm ? take(size_t(p.restart) * L * (mixed ? 4 : 8)) : 0;
+  lo.Z = gm ? take(size_t(p.restart) * L * 8) : 0;
+  lo.Zf = (gm && mixed) ? take(size_t(p.restart) * L * 4) : 0;
   lo.T = take(Nc * 16);
   lo.Tf = take(Nc * 8);
   lo.total = off;
@@ -248,11 +258,44 @@ struct fids_problem {
   std::vector<std::vector<float2>> keepf;
 };
 
+struct fids_batch {
+  BatchLayout bl;
+  int32_t count = 0;
+  int64_t M = 0;
+  int64_t level = 0;
+  bool poisoned = false;
+  bool graph_mode = false;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Prob* dprobs = nullptr;
+  int* dstatus = nullptr;
+  fids_step_info* dinfo = nullptr;
+  size_t lds = 0;
+  std::vector<Prob> hprobs;
+  std::vector<fids_problem*> members;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t cap_stream = nullptr;   // capture needs a stream other than the legacy default
+  ~fids_batch() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (fids_problem* h : members) delete h;
+  }
+};
+
 namespace {
 
-#define HIPCHK(x)                          \
-  do {                                     \
-    if ((x) != hipSuccess) return FIDS_EDEVICE; \
+// Records the call site and message of a failed HIP call (fids_last_error).
+thread_local char g_last_error[256] = "";
+bool hip_bad(hipError_t e, int line) {
+  if (e == hipSuccess) return false;
+  std::snprintf(g_last_error, sizeof(g_last_error), "fids_api.cpp:%d: %s (%d)", line, hipGetErrorString(e),
+                int(e));
+  return true;
+}
+
+#define HIPCHK(x)                                    \
+  do {                                               \
+    if (hip_bad((x), __LINE__)) return FIDS_EDEVICE; \
   } while (0)
 
 template <typename T>
@@ -294,7 +337,7 @@ int ensure_symbols(fids_problem* h) {
 int launch_wait(fids_problem* h, const Prob& hd, Prob* d, int m_begin, int m_end, int hist_lo, int ckpt_on,
                 int stat[2]) {
   HIPCHK(hipMemsetAsync(h->dabort, 0, sizeof(int), h->stream));
-  HIPCHK(fids::launch_levels(d, 1, hd.ng + hd.nh, h->lds, m_begin, m_end, hist_lo, ckpt_on, h->timeout_ticks,
+  HIPCHK(fids::launch_levels(hd, d, 1, hd.ng + hd.nh, h->lds, m_begin, m_end, hist_lo, ckpt_on, h->timeout_ticks,
                              h->dabort, h->stream));
   HIPCHK(hipMemcpyAsync(stat, hd.status, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -350,47 +393,22 @@ int restore_segment(fids_problem* h, int a) {
   return FIDS_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int fids_params_default(fids_params* p) {
-  if (!p) return FIDS_EINVAL;
-  std::memset(p, 0, sizeof(*p));
-  p->alpha = 1.5; p->gamma = 0.5; p->l = 1.0; p->T = 1.0;
-  p->n = 255; p->M = 64; p->r = 3.0; p->mu = 0.0;
-  p->soe_tol = 1e-10; p->krylov_tol = 1e-12; p->krylov_maxit = 200; p->restart = 20;
-  p->solver = FIDS_BICGSTAB; p->precision = FIDS_FP64; p->precond = FIDS_STRANG;
-  p->kappa_time_dependent = 1; p->x0_mode = 0; p->store_states = 0; p->wg_count = 0;
-  p->soe_helpers = -1; p->checkpoint_every = 0;
-  return FIDS_OK;
+// Parameter overrides of a batch member.
+void batch_params(fids_params& p) {
+  p.wg_count = 1;
+  p.soe_helpers = 0;
+  p.checkpoint_every = 0;
+  p.store_states = 0;
 }
 
-const char* fids_strerror(int s) {
-  switch (s) {
-    case FIDS_OK: return "ok";
-    case FIDS_EINVAL: return "invalid argument";
-    case FIDS_EDEVICE: return "HIP device error";
-    case FIDS_ENOCONV: return "Krylov solver did not converge";
-    case FIDS_ENUMERIC: return "non-finite value on the device";
-    case FIDS_ESTATE: return "call not valid in the current state";
-    default: return "unknown status";
-  }
-}
-
-int fids_workspace_size(const fids_params* p, size_t* bytes) {
-  if (!p || !bytes) return FIDS_EINVAL;
-  Shapes sh;
-  if (shapes_of(*p, sh, nullptr) != FIDS_OK) return FIDS_EINVAL;
-  *bytes = make_layout(*p, sh).total;
-  return FIDS_OK;
-}
-
-int fids_init_problem(const fids_params* p, const double* kappa_d, const double* f_d, const double* phi_d,
-                      void* ws_d, size_t ws_bytes, void* hip_stream, fids_problem** out) {
-  if (!p || !kappa_d || !f_d || !phi_d || !ws_d || !out) return FIDS_EINVAL;
-  if (reinterpret_cast<uintptr_t>(ws_d) % kAlign) return FIDS_EINVAL;
-  *out = nullptr;
+// Set-up of one problem.  A batch member (batch = true) runs on a single
+// workgroup (ng = 1, no helpers, no snapshots); the batch sets the LDS limit
+// and synchronises once for all of its members.
+int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, const double* phi_d,
+              void* ws_d, size_t ws_bytes, void* hip_stream, bool batch, fids_problem** out) {
+  fids_params pb = *pin;
+  if (batch) batch_params(pb);
+  const fids_params* p = &pb;
   fids_problem* h = new (std::nothrow) fids_problem();
   if (!h) return FIDS_EINVAL;
   h->prm = *p;
@@ -408,7 +426,7 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
   const HostTables& t = h->tab;
   int st = FIDS_OK;
   auto fail = [&](int code) { delete h; return code; };
-  if (hipMemsetAsync(ws, 0, lo.total, h->stream) != hipSuccess) return fail(FIDS_EDEVICE);
+  if (hip_bad(hipMemsetAsync(ws, 0, lo.total, h->stream), __LINE__)) return fail(FIDS_EDEVICE);
   // tables
   st |= upload(h, lo.beta, t.beta.data(), t.beta.size() * 8);
   st |= upload(h, lo.tau, t.tau.data(), t.tau.size() * 8);
@@ -456,10 +474,9 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
   for (int i = 0; i < 3; ++i) hp.u[i] = at<double>(ws, lo.u[i]);
   hp.F = at<double>(ws, lo.F); hp.kap = at<double>(ws, lo.kap);
   for (int i = 0; i < 10; ++i) hp.vec[i] = at<double>(ws, lo.vec[i]);
-  const bool mixed = p->precision == FIDS_MIXED;
   hp.V = lo.V ? at<double>(ws, lo.V) : nullptr;
-  hp.zd = (lo.Z && !mixed) ? at<double>(ws, lo.Z) : nullptr;
-  hp.zf = (lo.Z && mixed) ? at<float>(ws, lo.Z) : nullptr;
+  hp.zd = lo.Z ? at<double>(ws, lo.Z) : nullptr;
+  hp.zf = lo.Zf ? at<float>(ws, lo.Zf) : nullptr;
   hp.uhist = lo.uhist ? at<double>(ws, lo.uhist) : nullptr;
   hp.T = at<double2>(ws, lo.T); hp.Tf = at<float2>(ws, lo.Tf);
   hp.ckpt_every = std::max(p->checkpoint_every, 0);
@@ -484,17 +501,24 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
   j.identity = p->precond == FIDS_NONE;
   h->dj = at<SymJob>(ws, lo.job);
   h->lds = fids::level_lds_bytes(hp);
-  if (h->lds > 65536 && fids::set_level_lds_limit(h->lds) != hipSuccess) return fail(FIDS_EDEVICE);
-  {
+  if (batch) {
+    hp.ng = 1;
+    hp.nh = 0;
+  } else {
+    if (h->lds > 65536 && hip_bad(fids::set_level_lds_limit(hp, h->lds), __LINE__)) return fail(FIDS_EDEVICE);
     // SOE helpers use the CUs the solver group leaves free (the launch must
     // stay co-resident)
     int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        fids::level_max_blocks(h->lds, &per_cu) != hipSuccess)
+    if (hip_bad(hipGetDevice(&dev), __LINE__) ||
+        hip_bad(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), __LINE__) ||
+        hip_bad(fids::level_max_blocks(hp, h->lds, &per_cu), __LINE__))
       return fail(FIDS_EDEVICE);
     const int resident = cus * std::max(per_cu, 0);
-    if (resident < hp.ng) return fail(FIDS_EDEVICE);
+    if (resident < hp.ng) {
+      std::snprintf(g_last_error, sizeof(g_last_error),
+                    "fids_api.cpp:%d: %d workgroups cannot be co-resident (%d fit)", __LINE__, hp.ng, resident);
+      return fail(FIDS_EDEVICE);
+    }
     // auto = none: on MI355X at n = 65535 the helpers' stream slowed the
     // latency-bound solve more than it saved (976 -> 897 levels/s with 128)
     int nh = p->soe_helpers >= 0 ? p->soe_helpers : env_int("FIDS_HELPERS", 0);
@@ -524,19 +548,119 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
   }
   if (upload(h, lo.prob, &h->hp, sizeof(Prob)) != FIDS_OK) return fail(FIDS_EDEVICE);
   if (upload(h, lo.job, &h->hj, sizeof(SymJob)) != FIDS_OK) return fail(FIDS_EDEVICE);
-  if (fids::launch_init_state(hp, h->dp, h->stream) != hipSuccess) return fail(FIDS_EDEVICE);
+  if (hip_bad(fids::launch_init_state(hp, h->dp, h->stream), __LINE__)) return fail(FIDS_EDEVICE);
   int dev = 0, rate_khz = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return fail(FIDS_EDEVICE);
-  if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return fail(FIDS_EDEVICE);
+  if (hip_bad(hipGetDevice(&dev), __LINE__)) return fail(FIDS_EDEVICE);
+  if (hip_bad(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev), __LINE__)) return fail(FIDS_EDEVICE);
   h->timeout_ticks = (unsigned long long)(std::max(rate_khz, 1000)) * 1000ull * 4ull;  // 4 s
-  if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(FIDS_EDEVICE);
+  if (!batch && hip_bad(hipStreamSynchronize(h->stream), __LINE__)) return fail(FIDS_EDEVICE);
   *out = h;
   return FIDS_OK;
 }
 
+// ---------------------------------------------------------------- batch helpers
+int batch_layout(const fids_params* p, int32_t count, BatchLayout& bl) {
+  const int64_t M = p[0].M;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + std::max<size_t>(bytes, 1)); return o; };
+  bl.probs = take(size_t(count) * sizeof(Prob));
+  bl.status = take(size_t(count) * 4 * sizeof(int));
+  bl.info = take(size_t(count) * size_t(std::max<int64_t>(M, 1)) * sizeof(fids_step_info));
+  bl.head = off;
+  bl.member.resize(size_t(count));
+  bl.member_bytes.resize(size_t(count));
+  for (int32_t i = 0; i < count; ++i) {
+    // one kernel instance serves the batch: members share M and the solver variant
+    if (p[i].M != M || p[i].solver != p[0].solver || p[i].precision != p[0].precision) return FIDS_EINVAL;
+    fids_params q = p[i];
+    batch_params(q);
+    Shapes sh;
+    if (shapes_of(q, sh, nullptr) != FIDS_OK) return FIDS_EINVAL;
+    const size_t bytes = make_layout(q, sh).total;
+    bl.member[size_t(i)] = take(bytes);
+    bl.member_bytes[size_t(i)] = bytes;
+  }
+  bl.total = off;
+  return FIDS_OK;
+}
+
+int batch_symbols(fids_batch* b) {
+  for (fids_problem* h : b->members) {
+    if (h->symbols_ready) continue;
+    const int st = ensure_symbols(h);
+    if (st != FIDS_OK) return st;
+  }
+  return FIDS_OK;
+}
+
+// Waits for a batch launch over levels [m0, m1] and folds the members' status
+// words: the first failing member's status is returned; the batch level
+// advances to m1 only if every member completed it.
+int batch_finish(fids_batch* b, int m0, int m1) {
+  std::vector<int> w(size_t(b->count) * 4);
+  HIPCHK(hipMemcpyAsync(w.data(), b->dstatus, w.size() * sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  int st = FIDS_OK;
+  for (int32_t i = 0; i < b->count; ++i) {
+    const int si = w[size_t(i) * 4], last = w[size_t(i) * 4 + 1];
+    if (st == FIDS_OK && si != FIDS_OK) st = si;
+    if (st == FIDS_OK && last != m1) st = FIDS_EDEVICE;
+  }
+  (void)m0;
+  if (st == FIDS_OK) b->level = m1;
+  else b->poisoned = true;
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fids_params_default(fids_params* p) {
+  if (!p) return FIDS_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->alpha = 1.5; p->gamma = 0.5; p->l = 1.0; p->T = 1.0;
+  p->n = 255; p->M = 64; p->r = 3.0; p->mu = 0.0;
+  p->soe_tol = 1e-10; p->krylov_tol = 1e-12; p->krylov_maxit = 200; p->restart = 20;
+  p->solver = FIDS_BICGSTAB; p->precision = FIDS_FP64; p->precond = FIDS_STRANG;
+  p->kappa_time_dependent = 1; p->x0_mode = 0; p->store_states = 0; p->wg_count = 0;
+  p->soe_helpers = -1; p->checkpoint_every = 0;
+  return FIDS_OK;
+}
+
+const char* fids_last_error(void) { return g_last_error; }
+
+const char* fids_strerror(int s) {
+  switch (s) {
+    case FIDS_OK: return "ok";
+    case FIDS_EINVAL: return "invalid argument";
+    case FIDS_EDEVICE: return "HIP device error";
+    case FIDS_ENOCONV: return "Krylov solver did not converge";
+    case FIDS_ENUMERIC: return "non-finite value on the device";
+    case FIDS_ESTATE: return "call not valid in the current state";
+    default: return "unknown status";
+  }
+}
+
+int fids_workspace_size(const fids_params* p, size_t* bytes) {
+  if (!p || !bytes) return FIDS_EINVAL;
+  Shapes sh;
+  if (shapes_of(*p, sh, nullptr) != FIDS_OK) return FIDS_EINVAL;
+  *bytes = make_layout(*p, sh).total;
+  return FIDS_OK;
+}
+
+int fids_init_problem(const fids_params* p, const double* kappa_d, const double* f_d, const double* phi_d,
+                      void* ws_d, size_t ws_bytes, void* hip_stream, fids_problem** out) {
+  if (!p || !kappa_d || !f_d || !phi_d || !ws_d || !out) return FIDS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(ws_d) % kAlign) return FIDS_EINVAL;
+  *out = nullptr;
+  return init_impl(p, kappa_d, f_d, phi_d, ws_d, ws_bytes, hip_stream, false, out);
+}
+
 int fids_reset(fids_problem* h) {
   if (!h) return FIDS_EINVAL;
-  if (fids::launch_init_state(h->hp, h->dp, h->stream) != hipSuccess) return FIDS_EDEVICE;
+  HIPCHK(fids::launch_init_state(h->hp, h->dp, h->stream));
   HIPCHK(hipMemsetAsync(h->hp.F, 0, size_t(h->hp.nexp) * h->hp.vlen * 8, h->stream));
   HIPCHK(hipMemsetAsync(h->hp.H1, 0, size_t(2) * h->hp.vlen * 8, h->stream));
   HIPCHK(hipMemsetAsync(h->hp.sync2, 0, 4096, h->stream));
@@ -654,14 +778,162 @@ int fids_adjoint_report(const fids_problem* h, fids_step_info* per_step) {
   return FIDS_OK;
 }
 
-// ---------------------------------------------------------------- batched (not yet built)
-int fids_batch_workspace_size(const fids_params*, int32_t, size_t*) { return FIDS_EINVAL; }
-int fids_batch_init(const fids_params*, int32_t, const double* const*, const double* const*,
-                    const double* const*, void*, size_t, void*, fids_batch**) { return FIDS_EINVAL; }
-int fids_batch_step(fids_batch*, fids_step_info*) { return FIDS_EINVAL; }
-int fids_batch_solve_all(fids_batch*, double* const*, fids_step_info*) { return FIDS_EINVAL; }
-int fids_batch_reset(fids_batch*) { return FIDS_EINVAL; }
-int fids_batch_destroy(fids_batch*) { return FIDS_OK; }
+// ---------------------------------------------------------------- batched
+int fids_batch_workspace_size(const fids_params* p, int32_t count, size_t* bytes) {
+  if (!p || !bytes || count < 1) return FIDS_EINVAL;
+  BatchLayout bl;
+  const int st = batch_layout(p, count, bl);
+  if (st != FIDS_OK) return st;
+  *bytes = bl.total;
+  return FIDS_OK;
+}
+
+int fids_batch_init(const fids_params* p, int32_t count, const double* const* kappa_d, const double* const* f_d,
+                    const double* const* phi_d, void* ws_d, size_t ws_bytes, void* hip_stream, fids_batch** out) {
+  if (!p || count < 1 || !kappa_d || !f_d || !phi_d || !ws_d || !out) return FIDS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(ws_d) % kAlign) return FIDS_EINVAL;
+  *out = nullptr;
+  for (int32_t i = 0; i < count; ++i)
+    if (!kappa_d[i] || !f_d[i] || !phi_d[i]) return FIDS_EINVAL;
+  BatchLayout bl;
+  if (batch_layout(p, count, bl) != FIDS_OK) return FIDS_EINVAL;
+  if (ws_bytes < bl.total) return FIDS_EINVAL;
+  fids_batch* b = new (std::nothrow) fids_batch();
+  if (!b) return FIDS_EINVAL;
+  b->bl = bl;
+  b->count = count;
+  b->M = p[0].M;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->ws = static_cast<char*>(ws_d);
+  auto fail = [&](int code) { delete b; return code; };
+  if (hip_bad(hipMemsetAsync(b->ws, 0, bl.head, b->stream), __LINE__)) return fail(FIDS_EDEVICE);
+  b->dprobs = at<Prob>(b->ws, bl.probs);
+  b->dstatus = at<int>(b->ws, bl.status);
+  b->dinfo = at<fids_step_info>(b->ws, bl.info);
+  b->hprobs.resize(size_t(count));
+  b->members.assign(size_t(count), nullptr);
+  for (int32_t i = 0; i < count; ++i) {
+    fids_problem* h = nullptr;
+    const int st = init_impl(&p[i], kappa_d[i], f_d[i], phi_d[i], b->ws + bl.member[size_t(i)],
+                             bl.member_bytes[size_t(i)], hip_stream, true, &h);
+    if (st != FIDS_OK) return fail(st);
+    b->members[size_t(i)] = h;
+    // status words and level reports of every member sit together in the batch header
+    h->hp.status = b->dstatus + 4 * size_t(i);
+    h->hp.info = b->dinfo + size_t(i) * size_t(b->M);
+    h->dstatus = h->hp.status;
+    h->hp.g0 = i;
+    b->hprobs[size_t(i)] = h->hp;
+    b->lds = std::max(b->lds, h->lds);
+    if (upload(h, h->lo.prob, &h->hp, sizeof(Prob)) != FIDS_OK) return fail(FIDS_EDEVICE);
+  }
+  if (b->lds > 65536 && hip_bad(fids::set_level_lds_limit(b->hprobs[0], b->lds), __LINE__)) return fail(FIDS_EDEVICE);
+  if (hipMemcpyAsync(b->dprobs, b->hprobs.data(), size_t(count) * sizeof(Prob), hipMemcpyHostToDevice,
+                     b->stream) != hipSuccess) {
+    hip_bad(hipGetLastError(), __LINE__);
+    return fail(FIDS_EDEVICE);
+  }
+  if (hip_bad(hipStreamSynchronize(b->stream), __LINE__)) return fail(FIDS_EDEVICE);
+  const char* mode = std::getenv("FIDS_BATCH_MODE");
+  b->graph_mode = mode && std::strcmp(mode, "graph") == 0;
+  *out = b;
+  return FIDS_OK;
+}
+
+int fids_batch_step(fids_batch* b, fids_step_info* info) {
+  if (!b) return FIDS_EINVAL;
+  if (b->level >= b->M || b->poisoned) return FIDS_ESTATE;
+  int st = batch_symbols(b);
+  if (st != FIDS_OK) return st;
+  const int m = int(b->level + 1);
+  HIPCHK(fids::launch_levels_plain(b->hprobs[0], b->dprobs, b->count, b->count, b->lds, m, m, b->stream));
+  st = batch_finish(b, m, m);
+  if (info) {
+    std::vector<fids_step_info> all(size_t(b->count) * size_t(b->M));
+    HIPCHK(hipMemcpy(all.data(), b->dinfo, all.size() * sizeof(fids_step_info), hipMemcpyDeviceToHost));
+    for (int32_t i = 0; i < b->count; ++i) info[i] = all[size_t(i) * size_t(b->M) + size_t(m - 1)];
+  }
+  return st;
+}
+
+int fids_batch_solve_all(fids_batch* b, double* const* uT_d, fids_step_info* info) {
+  if (!b) return FIDS_EINVAL;
+  if (b->level >= b->M || b->poisoned) return FIDS_ESTATE;
+  int st = batch_symbols(b);
+  if (st != FIDS_OK) return st;
+  const int m0 = int(b->level + 1), M = int(b->M);
+  if (b->graph_mode) {
+    // one graph node per level, captured once for a solve from level 1
+    if (m0 == 1) {
+      if (!b->graph_exec) {
+        if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        for (int m = 1; m <= M; ++m)
+          if (hip_bad(fids::launch_levels_plain(b->hprobs[0], b->dprobs, b->count, b->count, b->lds, m, m, b->cap_stream),
+                      __LINE__)) {
+            (void)hipStreamEndCapture(b->cap_stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            return FIDS_EDEVICE;
+          }
+        HIPCHK(hipStreamEndCapture(b->cap_stream, &g));
+        const hipError_t e = hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (hip_bad(e, __LINE__)) { b->graph_exec = nullptr; return FIDS_EDEVICE; }
+      }
+      HIPCHK(hipGraphLaunch(b->graph_exec, b->stream));
+    } else {
+      for (int m = m0; m <= M; ++m)
+        HIPCHK(fids::launch_levels_plain(b->hprobs[0], b->dprobs, b->count, b->count, b->lds, m, m, b->stream));
+    }
+  } else {
+    HIPCHK(fids::launch_levels_plain(b->hprobs[0], b->dprobs, b->count, b->count, b->lds, m0, M, b->stream));
+  }
+  st = batch_finish(b, m0, M);
+  if (info) HIPCHK(hipMemcpy(info, b->dinfo, size_t(b->count) * size_t(M) * sizeof(fids_step_info),
+                             hipMemcpyDeviceToHost));
+  if (st != FIDS_OK) return st;
+  if (uT_d) {
+    for (int32_t i = 0; i < b->count; ++i) {
+      if (!uT_d[i]) continue;
+      const fids_problem* h = b->members[size_t(i)];
+      HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.u[M % 3], uT_d[i], b->stream));
+    }
+    HIPCHK(hipStreamSynchronize(b->stream));
+  }
+  return FIDS_OK;
+}
+
+int fids_batch_status(const fids_batch* b, int32_t* status, int64_t* last_level) {
+  if (!b || !status) return FIDS_EINVAL;
+  std::vector<int> w(size_t(b->count) * 4);
+  HIPCHK(hipMemcpy(w.data(), b->dstatus, w.size() * sizeof(int), hipMemcpyDeviceToHost));
+  for (int32_t i = 0; i < b->count; ++i) {
+    status[i] = w[size_t(i) * 4];
+    if (last_level) last_level[i] = w[size_t(i) * 4 + 1];
+  }
+  return FIDS_OK;
+}
+
+int fids_batch_reset(fids_batch* b) {
+  if (!b) return FIDS_EINVAL;
+  for (fids_problem* h : b->members) {
+    HIPCHK(fids::launch_init_state(h->hp, h->dp, b->stream));
+    HIPCHK(hipMemsetAsync(h->hp.F, 0, size_t(h->hp.nexp) * h->hp.vlen * 8, b->stream));
+    HIPCHK(hipMemsetAsync(h->hp.AU, 0, size_t(2) * h->hp.vlen * 8, b->stream));
+    h->symbols_ready = false;
+  }
+  HIPCHK(hipMemsetAsync(b->dstatus, 0, size_t(b->count) * 4 * sizeof(int), b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  b->level = 0;
+  b->poisoned = false;
+  return FIDS_OK;
+}
+
+int fids_batch_destroy(fids_batch* b) {
+  delete b;
+  return FIDS_OK;
+}
 
 // ---------------------------------------------------------------- introspection
 int fids_soe_nodes(double gamma, double delta, double T, double tol, int32_t cap, double* s, double* w,

@@ -521,13 +521,15 @@ template <> __device__ __forceinline__ float2* lbuf<float>(const Lds& L) { retur
   } while (0)
 
 __device__ __forceinline__ void write_info(const Prob& p, int rank, int m, int iters, int matvecs, double relres,
-                                           int status) {
+                                           int status, int fp64_iters = 0) {
   if (rank == 0 && threadIdx.x == 0) {
     fids_step_info in;
     in.m = m;
     in.iters = iters;
     in.matvecs = matvecs;
     in.relres = relres;
+    in.pc_fp64_iters = fp64_iters;
+    in.reserved = 0;
     p.info[m - 1] = in;
     p.status[0] = status;
     if (status == FIDS_OK) p.status[1] = m;
@@ -1480,38 +1482,57 @@ __device__ __forceinline__ void gm_F1(const Prob& p, int m, int rank, int jl, co
   }
 }
 
-// One level of FIDS with flexible GMRES(J), right preconditioning, pipelined
-// so that one Arnoldi step costs four group barriers.
+// Column pass of P^{-1} (FP64) on the residual VR: the start of a restart
+// cycle that continues with the FP64 preconditioner.
+__device__ __forceinline__ void phase_pc_col64(const Prob& p, int rank, const Lds& L) {
+  const Plan& pl = L.pl;
+  for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
+    const TileIdx t = tile_idx(pl, tile);
+    for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
+      int i0, sl;
+      item(pl, t, idx, i0, sl);
+      L.bd[sl] = ld2(p.vec[VR], t.toff + 2 * idx);
+    }
+    tileA_fft_store<double>(pl, tile, L.bd, p.T);
+  }
+}
+
+// Restart cycles of flexible GMRES(J) with the preconditioner in precision RP,
+// from the true residual r (VR, ||r||^2 = rr) whose P^{-1} column pass is in
+// pT<RP>.  With the FP32 preconditioner, a level still unconverged after its
+// first cycle continues with the FP64 preconditioner: flexible GMRES allows a
+// different preconditioner in every cycle, and the FP32 transforms cannot
+// resolve a preconditioner spectrum 1/(b_m' + kbar lambda_k) that spans more
+// than about 1e5.
 template <typename RP>
-__device__ __forceinline__ int level_fgmres(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L) {
+__device__ __forceinline__ int fgmres_cycles(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L, const Hess& H,
+                                             double bnorm, double rr, int it, int mv, int floor_hits,
+                                             bool est_conv, int it64) {
   const RP* Q = pQ<RP>(p, m);
   const double tol = p.tol;
   const int J = p.restart;
-  const Hess H = hess(L, J);
-  double bb, rr;
-  {
-    const int st = level_start(p, m, rank, ctl, L, sizeof(RP) == 4, bb, rr);
-    if (st != FIDS_OK) return st;
-  }
-  if (bad(bb) || bad(rr)) { write_info(p, rank, m, 0, 0, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
-  const double bnorm = sqrt(bb);
-  int it = 0, mv = (p.x0_mode != 0) ? 1 : 0;
-  int floor_hits = 0;       // cycles whose Arnoldi estimate met tol but the true residual did not
-  bool est_conv = false;
   double red1[1];
   for (;;) {                                   // restart cycles
     const double beta0 = sqrt(rr);
     if (est_conv && beta0 > tol * bnorm && ++floor_hits >= 2) {
       // the true FP64 residual has reached its attainable floor: accept and
       // report the true relative residual
-      write_info(p, rank, m, it, mv, beta0 / bnorm, FIDS_OK);
+      write_info(p, rank, m, it, mv, beta0 / bnorm, FIDS_OK, it64);
       return FIDS_OK;
     }
     if (beta0 <= tol * bnorm) {
-      write_info(p, rank, m, it, mv, bnorm > 0 ? beta0 / bnorm : 0.0, FIDS_OK);
+      write_info(p, rank, m, it, mv, bnorm > 0 ? beta0 / bnorm : 0.0, FIDS_OK, it64);
       return FIDS_OK;
     }
-    if (it >= p.maxit) { write_info(p, rank, m, it, mv, beta0 / bnorm, FIDS_ENOCONV); return FIDS_ENOCONV; }
+    if (it >= p.maxit) { write_info(p, rank, m, it, mv, beta0 / bnorm, FIDS_ENOCONV, it64); return FIDS_ENOCONV; }
+    if constexpr (sizeof(RP) == 4) {
+      if (p.qhat != nullptr && p.zd != nullptr && it >= J) {
+        phase_pc_col64(p, rank, L);
+        BARRIER();
+        return fgmres_cycles<double>(p, m, rank, ctl, L, H, bnorm, rr, it, mv, floor_hits, est_conv, 0);
+      }
+    }
+    const int it_cycle0 = it;
     if (threadIdx.x == 0) {
       for (int i = 0; i <= J; ++i) H.g[i] = 0.0;
       H.g[0] = beta0;
@@ -1536,7 +1557,7 @@ __device__ __forceinline__ int level_fgmres(const Prob& p, int m, int rank, Ctl&
       }
       double hs = 0.0;
       for (int i = 0; i <= j; ++i) hs += H.y[i] * H.y[i];
-      if (bad(red1[0]) || bad(hs)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
+      if (bad(red1[0]) || bad(hs)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC, it64); return FIDS_ENUMERIC; }
       const double e2 = red1[0] - hs;
       const double eta = e2 > 0.0 ? sqrt(e2) : 0.0;
       __syncthreads();
@@ -1574,6 +1595,7 @@ __device__ __forceinline__ int level_fgmres(const Prob& p, int m, int rank, Ctl&
       phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd, L);    // A z_{j+1} (rows)
       BARRIER();
     }
+    if (sizeof(RP) == 8 && p.precision == FIDS_MIXED) it64 += it - it_cycle0;
     __syncthreads();
     if (threadIdx.x == 0) lsq_solve(H, jl);
     __syncthreads();
@@ -1590,19 +1612,41 @@ __device__ __forceinline__ int level_fgmres(const Prob& p, int m, int rank, Ctl&
       reduce_slots<1>(p, sl, red1);
     }
     rr = red1[0];
-    if (bad(rr)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
+    if (bad(rr)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC, it64); return FIDS_ENUMERIC; }
   }
 }
 
-// ------------------------------------------------------------- level kernel
+// One level of FIDS with flexible GMRES(J), right preconditioning, pipelined
+// so that one Arnoldi step costs four group barriers.
+template <typename RP>
+__device__ __forceinline__ int level_fgmres(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L) {
+  const Hess H = hess(L, p.restart);
+  double bb, rr;
+  {
+    const int st = level_start(p, m, rank, ctl, L, sizeof(RP) == 4, bb, rr);
+    if (st != FIDS_OK) return st;
+  }
+  if (bad(bb) || bad(rr)) { write_info(p, rank, m, 0, 0, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
+  return fgmres_cycles<RP>(p, m, rank, ctl, L, H, sqrt(bb), rr, 0, (p.x0_mode != 0) ? 1 : 0, 0, false, 0);
+}
+
+// Level solver variants; each kernel instance holds one, so that its register
+// allocation follows that path alone.
+enum { VAR_BICG = 0, VAR_GM64 = 1, VAR_GM32 = 2, VAR_COUNT = 3 };
+
+template <int VAR>
+__device__ __forceinline__ int level_solve(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L) {
+  if constexpr (VAR == VAR_BICG) return level_bicgstab(p, m, rank, ctl, L);
+  else if constexpr (VAR == VAR_GM32) return level_fgmres<float>(p, m, rank, ctl, L);
+  else return level_fgmres<double>(p, m, rank, ctl, L);
+}
+
 // Adjoint level m: transposed solve, reversed history step, A u^m for the
 // kappa gradient (finished by the next level's right-hand side phase or by
 // the flush after the launch's last level).
+template <int VAR>
 __device__ __forceinline__ int level_adjoint(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L) {
-  int st;
-  if (p.solver == FIDS_BICGSTAB) st = level_bicgstab(p, m, rank, ctl, L);
-  else if (p.precision == FIDS_MIXED) st = level_fgmres<float>(p, m, rank, ctl, L);
-  else st = level_fgmres<double>(p, m, rank, ctl, L);
+  const int st = level_solve<VAR>(p, m, rank, ctl, L);
   if (st != FIDS_OK) return st;
   phase_adj_post(p, m, rank, L, ctl);
   BARRIER();
@@ -1612,14 +1656,23 @@ __device__ __forceinline__ int level_adjoint(const Prob& p, int m, int rank, Ctl
 }
 
 // Persistent level kernel.  Forward descriptors advance m = m_begin..m_end;
-// adjoint descriptors run m = m_begin down to m_end (m_begin >= m_end).
+// adjoint descriptors (ADJ) run m = m_begin down to m_end (m_begin >= m_end).
+template <int VAR, bool ADJ>
 __global__ void __launch_bounds__(kThreads) k_levels(const Prob* probs, int nprob, int m_begin, int m_end,
                                                      int hist_lo, int ckpt_on, unsigned long long timeout,
                                                      int* abort_flag) {
   extern __shared__ double2 dyn[];
+  // descriptors are sorted by their first workgroup g0
   int pid = 0;
-  for (int q = 0; q < nprob; ++q)
-    if (int(blockIdx.x) >= probs[q].g0) pid = q;
+  {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (int(blockIdx.x) >= probs[mid].g0) lo = mid;
+      else hi = mid - 1;
+    }
+    pid = lo;
+  }
   const Prob& p = probs[pid];
   const int rank = int(blockIdx.x) - p.g0;
   if (rank < 0 || rank >= p.ng + p.nh) return;
@@ -1668,10 +1721,10 @@ __global__ void __launch_bounds__(kThreads) k_levels(const Prob* probs, int npro
   ctl.ckpt_on = ckpt_on;
   ctl.pending = 0;
   if (threadIdx.x == 0) ctl.gen = __hip_atomic_load(&p.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (p.adjoint) {
+  if constexpr (ADJ) {
     for (int m = m_begin; m >= m_end; --m) {
       ctl.pending = m < m_begin;
-      const int st = level_adjoint(p, m, rank, ctl, L);
+      const int st = level_adjoint<VAR>(p, m, rank, ctl, L);
       if (st != FIDS_OK) {
         if (rank == 0 && threadIdx.x == 0 && st == FIDS_EDEVICE) p.status[0] = FIDS_EDEVICE;
         return;
@@ -1685,10 +1738,7 @@ __global__ void __launch_bounds__(kThreads) k_levels(const Prob* probs, int npro
     return;
   }
   for (int m = m_begin; m <= m_end; ++m) {
-    int st;
-    if (p.solver == FIDS_BICGSTAB) st = level_bicgstab(p, m, rank, ctl, L);
-    else if (p.precision == FIDS_MIXED) st = level_fgmres<float>(p, m, rank, ctl, L);
-    else st = level_fgmres<double>(p, m, rank, ctl, L);
+    const int st = level_solve<VAR>(p, m, rank, ctl, L);
     if (st != FIDS_OK) {
       if (rank == 0 && threadIdx.x == 0) {
         if (st == FIDS_EDEVICE) p.status[0] = FIDS_EDEVICE;
@@ -1912,23 +1962,46 @@ hipError_t launch_symbols(const SymJob& job, const SymJob* d, int m0, int cnt, h
   return hipGetLastError();
 }
 
-hipError_t level_max_blocks(size_t lds_bytes, int* per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, reinterpret_cast<const void*>(k_levels), kThreads,
-                                                      lds_bytes);
+// The kernel instance of a descriptor's solver variant and direction.
+static const void* level_kernel(const Prob& h) {
+  static const void* const table[VAR_COUNT][2] = {
+      {reinterpret_cast<const void*>(k_levels<VAR_BICG, false>), reinterpret_cast<const void*>(k_levels<VAR_BICG, true>)},
+      {reinterpret_cast<const void*>(k_levels<VAR_GM64, false>), reinterpret_cast<const void*>(k_levels<VAR_GM64, true>)},
+      {reinterpret_cast<const void*>(k_levels<VAR_GM32, false>), reinterpret_cast<const void*>(k_levels<VAR_GM32, true>)}};
+  const int var = h.solver == FIDS_BICGSTAB ? VAR_BICG : (h.precision == FIDS_MIXED ? VAR_GM32 : VAR_GM64);
+  return table[var][h.adjoint ? 1 : 0];
 }
 
-hipError_t set_level_lds_limit(size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_levels),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+hipError_t level_max_blocks(const Prob& h, size_t lds_bytes, int* per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, level_kernel(h), kThreads, lds_bytes);
 }
 
-hipError_t launch_levels(const Prob* probs, int nprob, int total_wg, size_t lds_bytes, int m_begin,
-                         int m_end, int hist_lo, int ckpt_on, unsigned long long timeout_ticks, int* abort_flag,
-                         hipStream_t s) {
+hipError_t set_level_lds_limit(const Prob& h, size_t bytes) {
+  Prob a = h;
+  a.adjoint = 0;
+  hipError_t e = hipFuncSetAttribute(level_kernel(a), hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  if (e != hipSuccess) return e;
+  a.adjoint = 1;
+  return hipFuncSetAttribute(level_kernel(a), hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
+hipError_t launch_levels_plain(const Prob& h, const Prob* probs, int nprob, int total_wg, size_t lds_bytes,
+                               int m_begin, int m_end, hipStream_t s) {
+  int hist_lo = -1, ckpt_on = 0;
+  unsigned long long timeout_ticks = 0;
+  int* abort_flag = nullptr;
   void* args[] = {(void*)&probs, (void*)&nprob, (void*)&m_begin, (void*)&m_end, (void*)&hist_lo,
                   (void*)&ckpt_on, (void*)&timeout_ticks, (void*)&abort_flag};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_levels), dim3(total_wg), dim3(kThreads),
-                                    args, static_cast<unsigned int>(lds_bytes), s);
+  return hipLaunchKernel(level_kernel(h), dim3(total_wg), dim3(kThreads), args, lds_bytes, s);
+}
+
+hipError_t launch_levels(const Prob& h, const Prob* probs, int nprob, int total_wg, size_t lds_bytes,
+                         int m_begin, int m_end, int hist_lo, int ckpt_on, unsigned long long timeout_ticks,
+                         int* abort_flag, hipStream_t s) {
+  void* args[] = {(void*)&probs, (void*)&nprob, (void*)&m_begin, (void*)&m_end, (void*)&hist_lo,
+                  (void*)&ckpt_on, (void*)&timeout_ticks, (void*)&abort_flag};
+  return hipLaunchCooperativeKernel(level_kernel(h), dim3(total_wg), dim3(kThreads), args,
+                                    static_cast<unsigned int>(lds_bytes), s);
 }
 
 }  // namespace fids

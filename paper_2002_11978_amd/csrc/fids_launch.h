@@ -24,18 +24,27 @@ size_t symbols_lds_bytes(const SymJob& job);
 
 // Advances every problem in `probs` (device array of `nprob` descriptors whose
 // workgroup groups tile [0, total_wg)) over levels [m_begin, m_end] in one
-// cooperative launch (adjoint descriptors: m_begin down to m_end).
+// cooperative launch (adjoint descriptors: m_begin down to m_end).  The
+// kernel instance follows the host copy `h` (all descriptors share its solver
+// variant and direction).
 // hist_lo >= 0 stores u^k at uhist[k - hist_lo] (forward) / reads it from
 // there (adjoint); ckpt_on writes the forward segment snapshots.
-hipError_t launch_levels(const Prob* probs, int nprob, int total_wg, size_t lds_bytes,
+hipError_t launch_levels(const Prob& h, const Prob* probs, int nprob, int total_wg, size_t lds_bytes,
                          int m_begin, int m_end, int hist_lo, int ckpt_on,
                          unsigned long long timeout_ticks, int* abort_flag, hipStream_t s);
 
-// Co-resident workgroups of the level kernel per CU for a given LDS size.
-hipError_t level_max_blocks(size_t lds_bytes, int* per_cu);
+// Ordinary (non-cooperative) launch for descriptors that all have one
+// workgroup (ng = 1, no helpers): no workgroup ever waits for another, so the
+// launch may be captured in a HIP graph.
+hipError_t launch_levels_plain(const Prob& h, const Prob* probs, int nprob, int total_wg, size_t lds_bytes,
+                               int m_begin, int m_end, hipStream_t s);
 
-// Raises the dynamic-LDS limit of the level kernel.
-hipError_t set_level_lds_limit(size_t bytes);
+// Co-resident workgroups per CU of the level kernel instance of `h` (its
+// solver variant and direction) for a given LDS size.
+hipError_t level_max_blocks(const Prob& h, size_t lds_bytes, int* per_cu);
+
+// Raises the dynamic-LDS limit of the forward and adjoint instances of `h`'s variant.
+hipError_t set_level_lds_limit(const Prob& h, size_t bytes);
 
 // Natural-layout [n] array into a tile-major vector (zero padding).
 hipError_t launch_from_natural(const Prob& h, const Prob* d, const double* src, double* dst, hipStream_t s);

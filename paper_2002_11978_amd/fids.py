@@ -38,13 +38,19 @@ class Params(ctypes.Structure):
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("iters", ctypes.c_int32), ("matvecs", ctypes.c_int32),
-                ("relres", ctypes.c_double)]
+                ("relres", ctypes.c_double), ("pc_fp64_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class FidsError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
-        super().__init__(f"{where}: {strerror(status)} ({status})")
+        detail = ""
+        if status == FIDS_EDEVICE:
+            try:
+                detail = " [" + lib().fids_last_error().decode() + "]"
+            except Exception:
+                pass
+        super().__init__(f"{where}: {strerror(status)} ({status}){detail}")
 
 
 _lib = None
@@ -64,6 +70,7 @@ _SIGS = {
     "fids_prepare": (ctypes.c_int, [_P]),
     "fids_destroy": (ctypes.c_int, [_P]),
     "fids_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "fids_last_error": (ctypes.c_char_p, []),
     "fids_batch_workspace_size": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32,
                                                  ctypes.POINTER(ctypes.c_size_t)]),
     "fids_batch_init": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(_P),
@@ -71,6 +78,7 @@ _SIGS = {
                                        ctypes.POINTER(_P)]),
     "fids_batch_step": (ctypes.c_int, [_P, ctypes.POINTER(StepInfo)]),
     "fids_batch_solve_all": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(StepInfo)]),
+    "fids_batch_status": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
     "fids_batch_reset": (ctypes.c_int, [_P]),
     "fids_batch_destroy": (ctypes.c_int, [_P]),
     "fids_soe_nodes": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -88,6 +96,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2002_11978_amd.build`")
+        # torch's wheel carries its own HIP runtime (same soname, different
+        # file).  Loading torch first makes libfids bind to that runtime;
+        # loading libfids first would put a second HIP and HSA runtime in the
+        # process, and device pointers and streams would cross between them.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
@@ -267,6 +283,85 @@ class Problem:
     def close(self):
         if getattr(self, "h", None):
             lib().fids_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent problems of eq. (1.1) advanced together (one workgroup
+    each, one launch per solve or per level).
+
+    params: list of Params (all with the same M); kappas, fs, phis: lists of
+    float64 device tensors, borrowed for the lifetime of the batch.
+    """
+
+    def __init__(self, params, kappas, fs, phis, stream=None):
+        import torch
+        self.torch = torch
+        count = len(params)
+        if not (len(kappas) == len(fs) == len(phis) == count) or count < 1:
+            raise ValueError("params, kappas, fs and phis must have the same nonzero length")
+        for lst in (kappas, fs, phis):
+            for t in lst:
+                if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                    raise ValueError("batch arrays must be contiguous float64 device tensors")
+        self.count = count
+        self.params = (Params * count)(*params)
+        self.kappas, self.fs, self.phis = list(kappas), list(fs), list(phis)
+        self.device = kappas[0].device
+        self.M = int(params[0].M)
+        self.ns = [int(p.n) for p in params]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nb = ctypes.c_size_t(0)
+        _check(lib().fids_batch_workspace_size(self.params, count, ctypes.byref(nb)), "fids_batch_workspace_size")
+        self.ws_bytes = nb.value
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        arr = lambda ts: (_P * count)(*[t.data_ptr() for t in ts])
+        h = ctypes.c_void_p(0)
+        _check(lib().fids_batch_init(self.params, count, arr(self.kappas), arr(self.fs), arr(self.phis),
+                                     _ptr(self.ws), self.ws_bytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                     ctypes.byref(h)), "fids_batch_init")
+        self.h = h
+
+    def _reports(self, infos):
+        return [[LevelReport(i.m, i.iters, i.matvecs, i.relres) for i in infos[p * self.M:(p + 1) * self.M]]
+                for p in range(self.count)]
+
+    def solve_all(self, want_uT=True):
+        torch = self.torch
+        outs = [torch.empty(n, dtype=torch.float64, device=self.device) for n in self.ns] if want_uT else None
+        ptrs = (_P * self.count)(*[t.data_ptr() for t in outs]) if want_uT else None
+        infos = (StepInfo * (self.count * self.M))()
+        st = lib().fids_batch_solve_all(self.h, ptrs, infos)
+        self.last_reports = self._reports(infos)
+        _check(st, "fids_batch_solve_all")
+        return outs, self.last_reports
+
+    def solve_all_raw(self, uT_ptrs=None, infos=None):
+        return lib().fids_batch_solve_all(self.h, uT_ptrs, infos)
+
+    def step(self):
+        infos = (StepInfo * self.count)()
+        _check(lib().fids_batch_step(self.h, infos), "fids_batch_step")
+        return [LevelReport(i.m, i.iters, i.matvecs, i.relres) for i in infos]
+
+    def status(self):
+        st = (ctypes.c_int32 * self.count)()
+        last = (ctypes.c_int64 * self.count)()
+        _check(lib().fids_batch_status(self.h, st, last), "fids_batch_status")
+        return list(st), list(last)
+
+    def reset(self):
+        _check(lib().fids_batch_reset(self.h), "fids_batch_reset")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fids_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -194,3 +194,16 @@ def batch_shapes(count=256, seed0=1000, n_lo=511, n_hi=16383):
         gamma = float(g.uniform(0.2, 0.8))
         out.append((n, alpha, gamma))
     return out
+
+
+def batch_member(p: int, M: int = 256, count_seed0: int = 1000, kappa_seed0: int = 2000,
+                 f_seed0: int = 3000, n_lo: int = 511, n_hi: int = 16383) -> Problem:
+    """Member p of the heterogeneous batch: (n, alpha, gamma) from
+    batch_shapes, grading r = (2 - gamma)/gamma, kappa seed 2000 + p, f seed
+    3000 + p."""
+    g = np.random.Generator(np.random.PCG64(count_seed0 + p))
+    n = int(round(math.exp(g.uniform(math.log(n_lo), math.log(n_hi)))))
+    alpha = float(g.uniform(1.1, 1.9))
+    gamma = float(g.uniform(0.2, 0.8))
+    return seeded(alpha, gamma, n, M, kappa_seed=kappa_seed0 + p, f_seed=f_seed0 + p,
+                  name=f"batch[{p}]")

@@ -12,6 +12,8 @@ import pytest
 import oracle
 from paper_2002_11978_amd import fids
 
+ROOT = __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__)))
+
 
 def test_library_exports_every_declared_function():
     L = fids.lib()
@@ -97,3 +99,15 @@ def test_soe_nodes_accuracy(gamma, delta, tol):
     err = oracle.soe_relative_error(s, w, gamma, min(delta, 1.0), 1.0, npts=20000)
     assert err <= tol * 1.05, err
     assert len(s) < 400
+
+
+def test_single_hip_runtime_in_process():
+    """The binding loads torch's HIP runtime before the library, so only one
+    HIP (and HSA) runtime is mapped into the process."""
+    import subprocess
+    import sys
+    code = ("from paper_2002_11978_amd import fids; fids.default_params();"
+            "maps = open('/proc/self/maps').read();"
+            "print(len({l.split()[-1] for l in maps.splitlines() if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, check=True)
+    assert out.stdout.strip() == "1"
