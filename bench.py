@@ -179,8 +179,8 @@ def batch_leg(tol, count):
     out = {"workload": f"{count} problems, n log-uniform in [511, 16383] (sum {sum(pb.n for pb in pbs)}), "
                        f"alpha~U(1.1,1.9), gamma~U(0.2,0.8), r=(2-gamma)/gamma, M={M}, seeded kappa(x,t), f(x,t)",
            "count": count, "M": M}
-    for name, cfg in (("fp64", dict(solver=1, precision=0, x0_mode=1)),
-                      ("mixed", dict(solver=1, precision=1, x0_mode=1))):
+    for name, cfg in (("fp64", dict(solver=1, precision=0, x0_mode=1, precond=2)),
+                      ("mixed", dict(solver=1, precision=1, x0_mode=1, precond=2))):
         params = [fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=M, r=pb.r, soe_tol=1e-10,
                                       krylov_tol=tol, krylov_maxit=500, **cfg) for pb in pbs]
         t0 = time.perf_counter()
@@ -202,7 +202,8 @@ def batch_leg(tol, count):
         fb = np.array([infos[i].pc_fp64_iters for i in range(count * M)])
         out[name] = {"problem_levels_per_s": count * M / best, "solve_ms": best * 1e3, "init_s": t_init,
                      "avg_iters": float(its.mean()), "levels_with_fp64_pc": int((fb > 0).sum()),
-                     "form": f"fgmres(20)-{'fp64' if cfg['precision'] == 0 else 'fp64/fp32pc'}-x0extrap"}
+                     "form": f"fgmres(20)-{'fp64' if cfg['precision'] == 0 else 'fp64/fp32pc'}-x0extrap-"
+                             "kappa-scaled-strang"}
         print(f"[bench] batch {name}: {count * M / best:.0f} problem-levels/s ({best * 1e3:.1f} ms), "
               f"its {its.mean():.2f}, fp64-pc levels {(fb > 0).sum()}", file=sys.stderr, flush=True)
         b.close()

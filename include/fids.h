@@ -69,6 +69,9 @@ extern "C" {
                           /* with the FP64 preconditioner                          */
 #define FIDS_STRANG   0   /* Strang circulant preconditioner, eq. (4.3)              */
 #define FIDS_NONE     1   /* no preconditioner (identity)                            */
+#define FIDS_STRANG_K 2   /* kappa-scaled Strang: P = K_m C_m, C_m the Strang        */
+                          /* circulant of b_m'/kbar_m I + A (same symbols as       */
+                          /* FIDS_STRANG, input scaled by kbar_m / kappa_i^m)      */
 
 /* Problem statement (1.1) plus discretisation and solver knobs.
  * Fill with fids_params_default() first, then set what differs. */
@@ -93,7 +96,7 @@ typedef struct fids_params {
     int32_t restart;      /* FGMRES Krylov dimension J (<= 32)                     */
     int32_t solver;       /* FIDS_BICGSTAB | FIDS_FGMRES                           */
     int32_t precision;    /* FIDS_FP64 | FIDS_MIXED (MIXED needs FIDS_FGMRES)      */
-    int32_t precond;      /* FIDS_STRANG | FIDS_NONE                               */
+    int32_t precond;      /* FIDS_STRANG | FIDS_NONE | FIDS_STRANG_K               */
     int32_t kappa_time_dependent; /* 1: kappa_d is [M][n]; 0: kappa_d is [n]      */
     int32_t x0_mode;      /* 0: zero initial guess (Sec. 5); 1: u^{m-1}            */
     int32_t store_states; /* 1: keep every u^m in the workspace (fids_adjoint     */

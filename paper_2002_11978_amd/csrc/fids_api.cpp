@@ -82,7 +82,7 @@ struct Layout {
   size_t tw1r, tw1rf, tw2r, tw2rf, tw1c, tw1cf, tw2c, tw2cf, twlo, twlof, twhi, twhif;
   size_t qhat, qhatf;
   size_t Tb, q, Tq;
-  size_t u[3], F, kap, vec[10], uhist, T, Tf, tau, V, Z, Zf, soec, H1, AU, sync2, hflag;
+  size_t u[3], F, kap, dsc, vec[10], uhist, T, Tf, tau, V, Z, Zf, soec, H1, AU, sync2, hflag;
   // adjoint: segment snapshots and the adjoint descriptor's state
   size_t ckpt, aprob, ainfo, astatus, ubar[3], yr[3], Fbar, alam, gk, AUa;
   int nck;          // snapshots held (levels kC + 1, k = 1..nck)
@@ -154,6 +154,7 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   for (int i = 0; i < 3; ++i) lo.u[i] = take(L * 8);
   lo.F = take(ne * L * 8);
   lo.kap = take(L * 8);
+  lo.dsc = take(L * 8);
   lo.H1 = take(2 * L * 8);
   lo.AU = take(2 * L * 8);
   for (int i = 0; i < 10; ++i) lo.vec[i] = take(L * 8);
@@ -472,7 +473,8 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   hp.qhatf = lo.qhatf ? at<float>(ws, lo.qhatf) : nullptr;
   hp.kappa = kappa_d; hp.f = f_d; hp.phi = phi_d;
   for (int i = 0; i < 3; ++i) hp.u[i] = at<double>(ws, lo.u[i]);
-  hp.F = at<double>(ws, lo.F); hp.kap = at<double>(ws, lo.kap);
+  hp.F = at<double>(ws, lo.F); hp.kap = at<double>(ws, lo.kap); hp.dsc = at<double>(ws, lo.dsc);
+  hp.kbar = at<double>(ws, lo.kbar);
   for (int i = 0; i < 10; ++i) hp.vec[i] = at<double>(ws, lo.vec[i]);
   hp.V = lo.V ? at<double>(ws, lo.V) : nullptr;
   hp.zd = lo.Z ? at<double>(ws, lo.Z) : nullptr;

@@ -66,6 +66,8 @@ struct Prob {
   double* u[3];                 // u^m lives in u[m % 3]
   double* F;                    // [ntiles][nexp][2*CT*N1]
   double* kap;                  // kappa^m, tile-major
+  double* dsc;                  // kbar_m / kappa^m, tile-major (kappa-scaled preconditioner)
+  const double* kbar;           // [M+1] mean of kappa^m
   double* vec[10];              // Krylov vectors (solver specific)
   float* zf;                    // FGMRES: Z basis in FP32 (mixed), [restart][vlen]
   double* zd;                   // FGMRES: Z basis in FP64, [restart][vlen]

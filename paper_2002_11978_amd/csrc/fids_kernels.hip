@@ -451,6 +451,14 @@ __device__ __forceinline__ double2 mask2(double2 v, int i0, int n) {
   return make_double2(i0 < n ? v.x : 0.0, i0 + 1 < n ? v.y : 0.0);
 }
 template <typename R> __device__ __forceinline__ Cx<R> tocx(double2 v) { return mk<R>(R(v.x), R(v.y)); }
+// Input of a P^{-1} application: with the kappa-scaled preconditioner
+// P = K_m C_m, P^{-1} v = C_m^{-1} K_m^{-1} v, and C_m^{-1} = kbar_m (b_m' I + kbar_m s(A))^{-1}
+// reuses the Strang symbol, so v is scaled by kbar_m / kappa_i^m (dsc, tile-major).
+__device__ __forceinline__ double2 pc_in(const Prob& p, int off, double2 v) {
+  if (p.precond != FIDS_STRANG_K) return v;
+  const double2 d = *reinterpret_cast<const double2*>(p.dsc + off);
+  return make_double2(v.x * d.x, v.y * d.y);
+}
 template <typename R> __device__ __forceinline__ double2 fromcx(Cx<R> v) { return make_double2(double(v.x), double(v.y)); }
 
 // views of the problem in the preconditioner precision R
@@ -675,6 +683,8 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
   const double* fm = p.f + size_t(m - 1) * p.n;
   const double* km = p.kappa + (p.kappa_td ? size_t(m - 1) * p.n : 0);
   const double* H1m = p.H1 + size_t(m & 1) * p.vlen;
+  const bool kscale = p.precond == FIDS_STRANG_K;
+  const double kb = kscale ? p.kbar[m] : 0.0;
   const double* Au1 = p.AU + size_t((m - 1) & 1) * p.vlen;
   double* Au2 = p.AU + size_t(m & 1) * p.vlen;   // A u^{m-2} in, A x0 out
   const int blk = 2 * pl.CT * pl.N1;
@@ -737,6 +747,7 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
           r0 = mask2(make_double2(b.x - (bm * x0.x + kk.x * ax.x), b.y - (bm * x0.y + kk.y * ax.y)), i0, p.n);
         }
         st2(p.kap, off, kk);
+        if (kscale) st2(p.dsc, off, mask2(make_double2(kb / kk.x, kb / kk.y), i0, p.n));
         if (ctl.hist_lo >= 0) st2(p.uhist + size_t(m - 1 - ctl.hist_lo) * p.vlen, off, a1);
       }
       st2(p.vec[VB], off, b);
@@ -745,13 +756,13 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
       if (fused) {
         st2(p.vec[VR], off, r0);
         acc[1] += r0.x * r0.x + r0.y * r0.y;
-        lbuf<RP>(L)[sl] = tocx<RP>(r0);
+        lbuf<RP>(L)[sl] = tocx<RP>(pc_in(p, off, r0));
       } else if (warm) {
         L.bd[sl] = x0;
       } else {
         st2(p.vec[VR], off, b);
         if (bicg) { st2(p.vec[VRH], off, b); st2(p.vec[VP], off, b); }
-        lbuf<RP>(L)[sl] = tocx<RP>(b);
+        lbuf<RP>(L)[sl] = tocx<RP>(pc_in(p, off, b));
       }
     }
     const int sls[2] = {SL_BB, SL_RR};
@@ -797,7 +808,7 @@ __device__ __forceinline__ void phase_r0(const Prob& p, int m, int rank, const L
       st2(p.vec[VR], off, r);
       if (bicg) { st2(p.vec[VRH], off, r); st2(p.vec[VP], off, r); }
       acc[0] += r.x * r.x + r.y * r.y;
-      lbuf<RP>(L)[sl] = tocx<RP>(r);
+      lbuf<RP>(L)[sl] = tocx<RP>(pc_in(p, off, r));
     }
     const int sl_rr[1] = {SL_RR};
     write_partials<1>(p, tile, sl_rr, acc);
@@ -845,6 +856,8 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
   double* x = p.u[m % 3];
   const double rho = (m + 2 <= p.M) ? p.tau[m + 1] / p.tau[m + 2] : 0.0;
   const double* km = p.kappa + (p.kappa_td ? size_t(m - 1) * p.n : 0);
+  const bool kscale = p.precond == FIDS_STRANG_K;
+  const double kb = kscale ? p.kbar[m] : 0.0;
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
     if (ctl.pending) tileC_load_ifft<double>(pl, tile, p.T, L.bd);
@@ -864,6 +877,7 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
           x0 = mask2(make_double2(a1.x + rho * (a1.x - a2.x), a1.y + rho * (a1.y - a2.y)), i0, p.n);
         }
         st2(p.kap, off, kk);
+        if (kscale) st2(p.dsc, off, mask2(make_double2(kb / kk.x, kb / kk.y), i0, p.n));
       }
       st2(p.vec[VB], off, b);
       st2(x, off, x0);
@@ -873,7 +887,7 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
       } else {
         st2(p.vec[VR], off, b);
         if (bicg) { st2(p.vec[VRH], off, b); st2(p.vec[VP], off, b); }
-        lbuf<RP>(L)[sl] = tocx<RP>(b);
+        lbuf<RP>(L)[sl] = tocx<RP>(pc_in(p, off, b));
       }
     }
     const int sls[1] = {SL_BB};
@@ -1047,6 +1061,7 @@ __device__ __forceinline__ void bi_s(const Prob& p, int rank, double alpha, cons
         st2(p.vec[VS], off, s);
         acc[0] += s.x * s.x + s.y * s.y;
         acc[1] += rh.x * s.x + rh.y * s.y;
+        s = pc_in(p, off, s);
       }
       L.bd[sl] = s;
     }
@@ -1083,6 +1098,7 @@ __device__ __forceinline__ void bi_update(const Prob& p, int m, int rank, double
         pn = mask2(make_double2(r.x + beta * (po.x - omega * v.x), r.y + beta * (po.y - omega * v.y)), i0, p.n);
         st2(p.vec[VP], off, pn);
         acc[0] += r.x * r.x + r.y * r.y;
+        pn = pc_in(p, off, pn);
       }
       L.bd[sl] = pn;
     }
@@ -1348,7 +1364,7 @@ __device__ __forceinline__ void gm_P1(const Prob& p, int m, int rank, int j, con
       }
       st2(p.vec[VV], off, w);
       accw[0] += w.x * w.x + w.y * w.y;
-      lbuf<RP>(L)[sl] = tocx<RP>(sh);
+      lbuf<RP>(L)[sl] = tocx<RP>(i0 < p.n ? pc_in(p, off, sh) : sh);
     }
     {
       const int sl[1] = {SL_GM + kMaxRestart + 1};
@@ -1491,7 +1507,7 @@ __device__ __forceinline__ void phase_pc_col64(const Prob& p, int rank, const Ld
     for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
       int i0, sl;
       item(pl, t, idx, i0, sl);
-      L.bd[sl] = ld2(p.vec[VR], t.toff + 2 * idx);
+      L.bd[sl] = i0 < p.n ? pc_in(p, t.toff + 2 * idx, ld2(p.vec[VR], t.toff + 2 * idx)) : make_double2(0.0, 0.0);
     }
     tileA_fft_store<double>(pl, tile, L.bd, p.T);
   }

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "fids.h")
 FIDS_OK, FIDS_EINVAL, FIDS_EDEVICE, FIDS_ENOCONV, FIDS_ENUMERIC, FIDS_ESTATE = 0, -1, -2, -3, -4, -5
 FIDS_BICGSTAB, FIDS_FGMRES = 0, 1
 FIDS_FP64, FIDS_MIXED = 0, 1
-FIDS_STRANG, FIDS_NONE = 0, 1
+FIDS_STRANG, FIDS_NONE, FIDS_STRANG_K = 0, 1, 2
 
 
 class Params(ctypes.Structure):
@@ -194,6 +194,7 @@ class LevelReport:
     iters: int
     matvecs: int
     relres: float
+    pc_fp64_iters: int = 0
 
 
 class Problem:
@@ -233,7 +234,7 @@ class Problem:
         u = self.torch.empty(self.n, dtype=self.torch.float64, device=self.device)
         info = StepInfo()
         _check(lib().fids_step(self.h, _ptr(u), ctypes.byref(info)), "fids_step")
-        return u, LevelReport(info.m, info.iters, info.matvecs, info.relres)
+        return u, LevelReport(info.m, info.iters, info.matvecs, info.relres, info.pc_fp64_iters)
 
     def solve_all(self, return_all=False, want_uT=True):
         torch = self.torch
@@ -241,7 +242,7 @@ class Problem:
         uall = torch.empty((self.M + 1, self.n), dtype=torch.float64, device=self.device) if return_all else None
         infos = (StepInfo * self.M)()
         st = lib().fids_solve_all(self.h, _ptr(uT), _ptr(uall), infos)
-        self.last_reports = [LevelReport(i.m, i.iters, i.matvecs, i.relres) for i in infos]
+        self.last_reports = [LevelReport(i.m, i.iters, i.matvecs, i.relres, i.pc_fp64_iters) for i in infos]
         _check(st, "fids_solve_all")
         return uT, uall, self.last_reports
 
@@ -272,7 +273,7 @@ class Problem:
     def adjoint_reports(self):
         infos = (StepInfo * self.M)()
         _check(lib().fids_adjoint_report(self.h, infos), "fids_adjoint_report")
-        return [LevelReport(i.m, i.iters, i.matvecs, i.relres) for i in infos]
+        return [LevelReport(i.m, i.iters, i.matvecs, i.relres, i.pc_fp64_iters) for i in infos]
 
     def reset(self):
         _check(lib().fids_reset(self.h), "fids_reset")
@@ -329,7 +330,7 @@ class Batch:
         self.h = h
 
     def _reports(self, infos):
-        return [[LevelReport(i.m, i.iters, i.matvecs, i.relres) for i in infos[p * self.M:(p + 1) * self.M]]
+        return [[LevelReport(i.m, i.iters, i.matvecs, i.relres, i.pc_fp64_iters) for i in infos[p * self.M:(p + 1) * self.M]]
                 for p in range(self.count)]
 
     def solve_all(self, want_uT=True):
@@ -348,7 +349,7 @@ class Batch:
     def step(self):
         infos = (StepInfo * self.count)()
         _check(lib().fids_batch_step(self.h, infos), "fids_batch_step")
-        return [LevelReport(i.m, i.iters, i.matvecs, i.relres) for i in infos]
+        return [LevelReport(i.m, i.iters, i.matvecs, i.relres, i.pc_fp64_iters) for i in infos]
 
     def status(self):
         st = (ctypes.c_int32 * self.count)()

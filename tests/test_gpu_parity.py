@@ -28,6 +28,9 @@ VARIANTS = [
     pytest.param(dict(solver=1, precision=0, x0_mode=0), id="fgmres-fp64-x0zero"),
     pytest.param(dict(solver=1, precision=0, x0_mode=1), id="fgmres-fp64-x0extrap"),
     pytest.param(dict(solver=1, precision=1, x0_mode=1), id="fgmres-mixed-x0extrap"),
+    pytest.param(dict(solver=0, precision=0, x0_mode=0, precond=2), id="bicgstab-fp64-x0zero-kpc"),
+    pytest.param(dict(solver=1, precision=0, x0_mode=1, precond=2), id="fgmres-fp64-x0extrap-kpc"),
+    pytest.param(dict(solver=1, precision=1, x0_mode=1, precond=2), id="fgmres-mixed-x0extrap-kpc"),
 ]
 
 
