@@ -214,9 +214,9 @@ int fids_batch_workspace_size(const fids_params* p, int32_t count, size_t* bytes
  * borrowed arrays kappa_d[i], f_d[i], phi_d[i] (host arrays of device
  * pointers).  All problems must share M, solver and precision (FIDS_EINVAL
  * otherwise); n, alpha, gamma, r, the tolerances, x0_mode, the
- * preconditioner and the fields may differ.  Each member runs on one
- * workgroup (store_states, checkpoint_every, soe_helpers and wg_count are
- * ignored). */
+ * preconditioner and the fields may differ.  The batch chooses each
+ * member's workgroups (fids_batch_groups); store_states, checkpoint_every,
+ * soe_helpers and wg_count are ignored. */
 int fids_batch_init(const fids_params* p, int32_t count, const double* const* kappa_d,
                     const double* const* f_d, const double* const* phi_d, void* ws_d,
                     size_t ws_bytes, void* hip_stream, fids_batch** out);
@@ -234,6 +234,13 @@ int fids_batch_solve_all(fids_batch* b, double* const* uT_d, fids_step_info* inf
  * last_level is not NULL, the last level member i completed.  Host arrays of
  * `count` entries. */
 int fids_batch_status(const fids_batch* b, int32_t* status, int64_t* last_level);
+
+/* Workgroups each member runs on (host array of `count`).  The batch places
+ * its members on the co-resident workgroups so that the slowest slot is as
+ * short as possible: members whose level costs more than that target get a
+ * group of several workgroups, the others are packed into one-workgroup
+ * slots that run their members one after another. */
+int fids_batch_groups(const fids_batch* b, int32_t* ng);
 
 /* Back to level 0 for every member (per-level symbols rebuilt on the next call). */
 int fids_batch_reset(fids_batch* b);

@@ -95,7 +95,7 @@ struct Layout {
 // Batch workspace: descriptors, status words and level reports of all
 // members, then one single-problem workspace per member.
 struct BatchLayout {
-  size_t probs, status, info, head, total;
+  size_t probs, status, info, abort_, head, total;
   std::vector<size_t> member, member_bytes;
 };
 
@@ -116,7 +116,9 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   lo.status = take(4 * sizeof(int));
   lo.bar = take(4096);
   lo.info = take(M * sizeof(fids_step_info));
-  lo.part = take(size_t(fids::SL_COUNT) * sh.pr.ntiles * sizeof(double));
+  // partial sums: one slot per column tile; sized for the finest split (CT = 1)
+  // so that the layout does not depend on the group size a batch assigns
+  lo.part = take(size_t(fids::SL_COUNT) * size_t(sh.pr.N2) * sizeof(double));
   lo.beta = take((M + 1) * 8);
   lo.tau = take((M + 1) * 8);
   lo.soec = take((M + 1) * 8);
@@ -272,8 +274,13 @@ struct fids_batch {
   int* dstatus = nullptr;
   fids_step_info* dinfo = nullptr;
   size_t lds = 0;
-  std::vector<Prob> hprobs;
+  int total_wg = 0;              // workgroups of one launch (sum of the slots' groups)
+  bool cooperative = false;      // some member has a group of more than one workgroup
+  int* dabort = nullptr;
+  unsigned long long timeout_ticks = 0;
+  std::vector<Prob> hprobs;      // descriptors in launch order (slots)
   std::vector<fids_problem*> members;
+  std::vector<int> groups;       // workgroups of each member's group
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t cap_stream = nullptr;   // capture needs a stream other than the legacy default
   ~fids_batch() {
@@ -395,8 +402,8 @@ int restore_segment(fids_problem* h, int a) {
 }
 
 // Parameter overrides of a batch member.
-void batch_params(fids_params& p) {
-  p.wg_count = 1;
+void batch_params(fids_params& p, int group = 1) {
+  p.wg_count = group;
   p.soe_helpers = 0;
   p.checkpoint_every = 0;
   p.store_states = 0;
@@ -406,9 +413,10 @@ void batch_params(fids_params& p) {
 // workgroup (ng = 1, no helpers, no snapshots); the batch sets the LDS limit
 // and synchronises once for all of its members.
 int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, const double* phi_d,
-              void* ws_d, size_t ws_bytes, void* hip_stream, bool batch, fids_problem** out) {
+              void* ws_d, size_t ws_bytes, void* hip_stream, int batch_group, fids_problem** out) {
+  const bool batch = batch_group > 0;
   fids_params pb = *pin;
-  if (batch) batch_params(pb);
+  if (batch) batch_params(pb, batch_group);
   const fids_params* p = &pb;
   fids_problem* h = new (std::nothrow) fids_problem();
   if (!h) return FIDS_EINVAL;
@@ -461,6 +469,7 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   hp.L = int(h->sh.L); hp.vlen = int(h->sh.L);
   fill_plan(hp.pl, h->sh.pr, 2, ws, lo, false);
   hp.g0 = 0;
+  hp.slot_first = 0;
   hp.ng = std::max(hp.pl.ntiles, hp.pl.nrg);
   hp.soec = at<double>(ws, lo.soec);
   hp.H1 = at<double>(ws, lo.H1);
@@ -504,7 +513,7 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   h->dj = at<SymJob>(ws, lo.job);
   h->lds = fids::level_lds_bytes(hp);
   if (batch) {
-    hp.ng = 1;
+    hp.ng = batch_group;
     hp.nh = 0;
   } else {
     if (h->lds > 65536 && hip_bad(fids::set_level_lds_limit(hp, h->lds), __LINE__)) return fail(FIDS_EDEVICE);
@@ -561,6 +570,83 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
 }
 
 // ---------------------------------------------------------------- batch helpers
+// Work of one level of a member, in units of the embedding length L (the
+// passes stream O(L) data each), and the extra cost of a group of k > 1
+// workgroups (about 50 group barriers per level at 1.5 us + 70 ns per
+// workgroup, which is worth about 260 + 12 k units at 0.29 us per unit on
+// one workgroup).
+double group_cost(double c, int k) { return c / k + (k > 1 ? 260.0 + 12.0 * k : 0.0); }
+
+// Schedule of a batch on R co-resident workgroups: members whose cost
+// exceeds the makespan target T get a group of k > 1 workgroups (powers of
+// two up to kmax); the others are packed first-fit-decreasing into
+// one-workgroup slots of capacity T.  The smallest feasible T is found by
+// bisection.  Returns the slots (group size, members in run order).
+struct Slot {
+  int ng;
+  std::vector<int> members;
+};
+
+bool schedule_at(double T, const std::vector<double>& c, const std::vector<int>& kmax, int R,
+                 std::vector<Slot>* out) {
+  std::vector<Slot> slots;
+  std::vector<int> small;
+  int total = 0;
+  for (size_t i = 0; i < c.size(); ++i) {
+    if (c[i] <= T) { small.push_back(int(i)); continue; }
+    int k = 2;
+    while (k <= kmax[i] && group_cost(c[i], k) > T) k *= 2;
+    if (k > kmax[i]) return false;
+    slots.push_back({k, {int(i)}});
+    total += k;
+    if (total > R) return false;
+  }
+  std::sort(small.begin(), small.end(), [&](int a, int b) { return c[size_t(a)] > c[size_t(b)]; });
+  std::vector<double> load;
+  std::vector<Slot> bins;
+  for (int i : small) {
+    size_t j = 0;
+    while (j < bins.size() && load[j] + c[size_t(i)] > T) ++j;
+    if (j == bins.size()) {
+      bins.push_back({1, {}});
+      load.push_back(0.0);
+      if (total + int(bins.size()) > R) return false;
+    }
+    bins[j].members.push_back(i);
+    load[j] += c[size_t(i)];
+  }
+  if (out) {
+    *out = slots;
+    out->insert(out->end(), bins.begin(), bins.end());
+  }
+  return true;
+}
+
+std::vector<Slot> schedule_batch(const std::vector<double>& c, const std::vector<int>& kmax, int R) {
+  double lo = 0.0, hi = 0.0;
+  for (size_t i = 0; i < c.size(); ++i) {
+    double best = c[i];
+    for (int k = 2; k <= kmax[i]; k *= 2) best = std::min(best, group_cost(c[i], k));
+    lo = std::max(lo, best);
+    hi += c[i];
+  }
+  std::vector<Slot> out;
+  if (!schedule_at(hi, c, kmax, R, &out)) {
+    // fewer workgroups than needed even with everything packed: one slot
+    out.assign(1, {1, {}});
+    for (size_t i = 0; i < c.size(); ++i) out[0].members.push_back(int(i));
+    return out;
+  }
+  if (schedule_at(lo, c, kmax, R, &out)) return out;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (schedule_at(mid, c, kmax, R, nullptr)) hi = mid;
+    else lo = mid;
+  }
+  schedule_at(hi, c, kmax, R, &out);
+  return out;
+}
+
 int batch_layout(const fids_params* p, int32_t count, BatchLayout& bl) {
   const int64_t M = p[0].M;
   size_t off = 0;
@@ -568,6 +654,7 @@ int batch_layout(const fids_params* p, int32_t count, BatchLayout& bl) {
   bl.probs = take(size_t(count) * sizeof(Prob));
   bl.status = take(size_t(count) * 4 * sizeof(int));
   bl.info = take(size_t(count) * size_t(std::max<int64_t>(M, 1)) * sizeof(fids_step_info));
+  bl.abort_ = take(sizeof(int));
   bl.head = off;
   bl.member.resize(size_t(count));
   bl.member_bytes.resize(size_t(count));
@@ -584,6 +671,15 @@ int batch_layout(const fids_params* p, int32_t count, BatchLayout& bl) {
   }
   bl.total = off;
   return FIDS_OK;
+}
+
+hipError_t batch_launch(fids_batch* b, int m0, int m1, hipStream_t s) {
+  if (!b->cooperative)
+    return fids::launch_levels_plain(b->hprobs[0], b->dprobs, b->count, b->total_wg, b->lds, m0, m1, s);
+  hipError_t e = hipMemsetAsync(b->dabort, 0, sizeof(int), s);
+  if (e != hipSuccess) return e;
+  return fids::launch_levels(b->hprobs[0], b->dprobs, b->count, b->total_wg, b->lds, m0, m1, -1, 0,
+                             b->timeout_ticks, b->dabort, s);
 }
 
 int batch_symbols(fids_batch* b) {
@@ -657,7 +753,7 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
   if (!p || !kappa_d || !f_d || !phi_d || !ws_d || !out) return FIDS_EINVAL;
   if (reinterpret_cast<uintptr_t>(ws_d) % kAlign) return FIDS_EINVAL;
   *out = nullptr;
-  return init_impl(p, kappa_d, f_d, phi_d, ws_d, ws_bytes, hip_stream, false, out);
+  return init_impl(p, kappa_d, f_d, phi_d, ws_d, ws_bytes, hip_stream, 0, out);
 }
 
 int fids_reset(fids_problem* h) {
@@ -812,24 +908,83 @@ int fids_batch_init(const fids_params* p, int32_t count, const double* const* ka
   b->dprobs = at<Prob>(b->ws, bl.probs);
   b->dstatus = at<int>(b->ws, bl.status);
   b->dinfo = at<fids_step_info>(b->ws, bl.info);
+  b->dabort = at<int>(b->ws, bl.abort_);
+  // costs, largest groups and an LDS bound (one-workgroup plans have the largest tiles)
+  std::vector<double> cost(static_cast<size_t>(count));
+  std::vector<int> kmax(static_cast<size_t>(count));
+  size_t lds_bound = 0;
+  Prob probe{};
+  for (int32_t i = 0; i < count; ++i) {
+    fids_params q = p[i];
+    batch_params(q, 1);
+    Shapes sh;
+    if (shapes_of(q, sh, nullptr) != FIDS_OK) return fail(FIDS_EINVAL);
+    cost[size_t(i)] = double(sh.L);
+    int k = 1;
+    while (k * 2 <= std::min(64, sh.pr.N2) && int64_t(k) * 2 * 1024 <= sh.Nc) k *= 2;
+    kmax[size_t(i)] = k;
+    probe.nexp = sh.nexp; probe.L = int(sh.L); probe.precision = q.precision; probe.solver = q.solver;
+    probe.pl.CT = sh.pr.CT; probe.pl.N1 = sh.pr.N1; probe.pl.N2 = sh.pr.N2; probe.pl.RU = sh.pr.RU;
+    const int tws = (ilog2i(sh.L) + 1) / 2;
+    probe.pl.twshift = tws; probe.pl.twmask = (1 << tws) - 1;
+    lds_bound = std::max(lds_bound, fids::level_lds_bytes(probe));
+  }
+  int resident = count;
+  {
+    int dev = 0, cus = 0, per_cu = 0;
+    probe.adjoint = 0;
+    if (lds_bound > 65536 && hip_bad(fids::set_level_lds_limit(probe, lds_bound), __LINE__)) return fail(FIDS_EDEVICE);
+    if (hip_bad(hipGetDevice(&dev), __LINE__) ||
+        hip_bad(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), __LINE__) ||
+        hip_bad(fids::level_max_blocks(probe, lds_bound, &per_cu), __LINE__))
+      return fail(FIDS_EDEVICE);
+    resident = std::max(1, cus * per_cu);
+  }
+  const std::vector<Slot> slots = schedule_batch(cost, kmax, resident);
   b->hprobs.resize(size_t(count));
   b->members.assign(size_t(count), nullptr);
-  for (int32_t i = 0; i < count; ++i) {
-    fids_problem* h = nullptr;
-    const int st = init_impl(&p[i], kappa_d[i], f_d[i], phi_d[i], b->ws + bl.member[size_t(i)],
-                             bl.member_bytes[size_t(i)], hip_stream, true, &h);
-    if (st != FIDS_OK) return fail(st);
-    b->members[size_t(i)] = h;
-    // status words and level reports of every member sit together in the batch header
-    h->hp.status = b->dstatus + 4 * size_t(i);
-    h->hp.info = b->dinfo + size_t(i) * size_t(b->M);
-    h->dstatus = h->hp.status;
-    h->hp.g0 = i;
-    b->hprobs[size_t(i)] = h->hp;
-    b->lds = std::max(b->lds, h->lds);
-    if (upload(h, h->lo.prob, &h->hp, sizeof(Prob)) != FIDS_OK) return fail(FIDS_EDEVICE);
+  b->groups.assign(size_t(count), 1);
+  int g0 = 0, desc = 0;
+  for (const Slot& sl : slots) {
+    const int first = desc;
+    for (int i : sl.members) {
+      fids_problem* h = nullptr;
+      const int st = init_impl(&p[i], kappa_d[i], f_d[i], phi_d[i], b->ws + bl.member[size_t(i)],
+                               bl.member_bytes[size_t(i)], hip_stream, sl.ng, &h);
+      if (st != FIDS_OK) return fail(st);
+      b->members[size_t(i)] = h;
+      b->groups[size_t(i)] = sl.ng;
+      // status words and level reports of every member sit together in the batch header
+      h->hp.status = b->dstatus + 4 * size_t(i);
+      h->hp.info = b->dinfo + size_t(i) * size_t(b->M);
+      h->dstatus = h->hp.status;
+      h->hp.g0 = g0;
+      h->hp.slot_first = first;
+      b->hprobs[size_t(desc)] = h->hp;
+      b->lds = std::max(b->lds, h->lds);
+      if (upload(h, h->lo.prob, &h->hp, sizeof(Prob)) != FIDS_OK) return fail(FIDS_EDEVICE);
+      ++desc;
+    }
+    g0 += sl.ng;
+    if (sl.ng > 1) b->cooperative = true;
   }
+  b->total_wg = g0;
   if (b->lds > 65536 && hip_bad(fids::set_level_lds_limit(b->hprobs[0], b->lds), __LINE__)) return fail(FIDS_EDEVICE);
+  if (b->cooperative) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hip_bad(hipGetDevice(&dev), __LINE__) ||
+        hip_bad(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), __LINE__) ||
+        hip_bad(fids::level_max_blocks(b->hprobs[0], b->lds, &per_cu), __LINE__))
+      return fail(FIDS_EDEVICE);
+    if (cus * per_cu < b->total_wg) {
+      std::snprintf(g_last_error, sizeof(g_last_error), "fids_api.cpp:%d: batch needs %d co-resident workgroups (%d fit)",
+                    __LINE__, b->total_wg, cus * per_cu);
+      return fail(FIDS_EDEVICE);
+    }
+    int rate_khz = 0;
+    if (hip_bad(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev), __LINE__)) return fail(FIDS_EDEVICE);
+    b->timeout_ticks = (unsigned long long)(std::max(rate_khz, 1000)) * 1000ull * 4ull;  // 4 s
+  }
   if (hipMemcpyAsync(b->dprobs, b->hprobs.data(), size_t(count) * sizeof(Prob), hipMemcpyHostToDevice,
                      b->stream) != hipSuccess) {
     hip_bad(hipGetLastError(), __LINE__);
@@ -837,7 +992,8 @@ int fids_batch_init(const fids_params* p, int32_t count, const double* const* ka
   }
   if (hip_bad(hipStreamSynchronize(b->stream), __LINE__)) return fail(FIDS_EDEVICE);
   const char* mode = std::getenv("FIDS_BATCH_MODE");
-  b->graph_mode = mode && std::strcmp(mode, "graph") == 0;
+  // a HIP graph holds ordinary launches only: one-workgroup members
+  b->graph_mode = mode && std::strcmp(mode, "graph") == 0 && !b->cooperative;
   *out = b;
   return FIDS_OK;
 }
@@ -848,7 +1004,7 @@ int fids_batch_step(fids_batch* b, fids_step_info* info) {
   int st = batch_symbols(b);
   if (st != FIDS_OK) return st;
   const int m = int(b->level + 1);
-  HIPCHK(fids::launch_levels_plain(b->hprobs[0], b->dprobs, b->count, b->count, b->lds, m, m, b->stream));
+  HIPCHK(batch_launch(b, m, m, b->stream));
   st = batch_finish(b, m, m);
   if (info) {
     std::vector<fids_step_info> all(size_t(b->count) * size_t(b->M));
@@ -872,8 +1028,7 @@ int fids_batch_solve_all(fids_batch* b, double* const* uT_d, fids_step_info* inf
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         for (int m = 1; m <= M; ++m)
-          if (hip_bad(fids::launch_levels_plain(b->hprobs[0], b->dprobs, b->count, b->count, b->lds, m, m, b->cap_stream),
-                      __LINE__)) {
+          if (hip_bad(batch_launch(b, m, m, b->cap_stream), __LINE__)) {
             (void)hipStreamEndCapture(b->cap_stream, &g);
             if (g) (void)hipGraphDestroy(g);
             return FIDS_EDEVICE;
@@ -886,10 +1041,10 @@ int fids_batch_solve_all(fids_batch* b, double* const* uT_d, fids_step_info* inf
       HIPCHK(hipGraphLaunch(b->graph_exec, b->stream));
     } else {
       for (int m = m0; m <= M; ++m)
-        HIPCHK(fids::launch_levels_plain(b->hprobs[0], b->dprobs, b->count, b->count, b->lds, m, m, b->stream));
+        HIPCHK(batch_launch(b, m, m, b->stream));
     }
   } else {
-    HIPCHK(fids::launch_levels_plain(b->hprobs[0], b->dprobs, b->count, b->count, b->lds, m0, M, b->stream));
+    HIPCHK(batch_launch(b, m0, M, b->stream));
   }
   st = batch_finish(b, m0, M);
   if (info) HIPCHK(hipMemcpy(info, b->dinfo, size_t(b->count) * size_t(M) * sizeof(fids_step_info),
@@ -917,12 +1072,19 @@ int fids_batch_status(const fids_batch* b, int32_t* status, int64_t* last_level)
   return FIDS_OK;
 }
 
+int fids_batch_groups(const fids_batch* b, int32_t* ng) {
+  if (!b || !ng) return FIDS_EINVAL;
+  for (int32_t i = 0; i < b->count; ++i) ng[i] = b->groups[size_t(i)];
+  return FIDS_OK;
+}
+
 int fids_batch_reset(fids_batch* b) {
   if (!b) return FIDS_EINVAL;
   for (fids_problem* h : b->members) {
     HIPCHK(fids::launch_init_state(h->hp, h->dp, b->stream));
     HIPCHK(hipMemsetAsync(h->hp.F, 0, size_t(h->hp.nexp) * h->hp.vlen * 8, b->stream));
     HIPCHK(hipMemsetAsync(h->hp.AU, 0, size_t(2) * h->hp.vlen * 8, b->stream));
+    HIPCHK(hipMemsetAsync(h->hp.bar, 0, 4 * sizeof(unsigned), b->stream));
     h->symbols_ready = false;
   }
   HIPCHK(hipMemsetAsync(b->dstatus, 0, size_t(b->count) * 4 * sizeof(int), b->stream));

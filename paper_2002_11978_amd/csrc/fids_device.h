@@ -47,6 +47,7 @@ struct Prob {
   int solver, precision, precond, kappa_td, x0_mode, maxit, restart, store_states;
   double tol;
   int g0, ng;                   // workgroups [g0, g0 + ng) cooperate on this problem
+  int slot_first;               // first descriptor of the slot of problems these workgroups run in turn
   int L, vlen;                  // embedding length and tile-major vector length (= L)
   Plan pl;                      // real-packed plan, Nc = L/2
   // set-up tables

@@ -1671,27 +1671,11 @@ __device__ __forceinline__ int level_adjoint(const Prob& p, int m, int rank, Ctl
   return FIDS_OK;
 }
 
-// Persistent level kernel.  Forward descriptors advance m = m_begin..m_end;
-// adjoint descriptors (ADJ) run m = m_begin down to m_end (m_begin >= m_end).
+// One problem's levels inside the level kernel (workgroup `rank` of its group).
 template <int VAR, bool ADJ>
-__global__ void __launch_bounds__(kThreads) k_levels(const Prob* probs, int nprob, int m_begin, int m_end,
-                                                     int hist_lo, int ckpt_on, unsigned long long timeout,
-                                                     int* abort_flag) {
-  extern __shared__ double2 dyn[];
-  // descriptors are sorted by their first workgroup g0
-  int pid = 0;
-  {
-    int lo = 0, hi = nprob - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (int(blockIdx.x) >= probs[mid].g0) lo = mid;
-      else hi = mid - 1;
-    }
-    pid = lo;
-  }
-  const Prob& p = probs[pid];
-  const int rank = int(blockIdx.x) - p.g0;
-  if (rank < 0 || rank >= p.ng + p.nh) return;
+__device__ __forceinline__ void run_member(const Prob& p, int rank, int m_begin, int m_end, int hist_lo,
+                                           int ckpt_on, unsigned long long timeout, int* abort_flag,
+                                           double2* dyn) {
   // LDS: [tab 3*nexp doubles][small][twiddles FP64][twiddles FP32][FP64 buffer][FP32 buffer]
   const int tab_c = (3 * p.nexp + 1) / 2;
   const int small_c = kSmallDoubles / 2;
@@ -1779,6 +1763,37 @@ __global__ void __launch_bounds__(kThreads) k_levels(const Prob* probs, int npro
         st2(dst, off, ld2(ue, off));
       }
     }
+  }
+}
+
+
+// Persistent level kernel.  Forward descriptors advance m = m_begin..m_end;
+// adjoint descriptors (ADJ) run m = m_begin down to m_end (m_begin >= m_end).
+// Descriptors are sorted by their first workgroup g0; consecutive descriptors
+// with the same g0 form a slot whose members the slot's workgroups run one
+// after the other (packed batch members).
+template <int VAR, bool ADJ>
+__global__ void __launch_bounds__(kThreads) k_levels(const Prob* probs, int nprob, int m_begin, int m_end,
+                                                     int hist_lo, int ckpt_on, unsigned long long timeout,
+                                                     int* abort_flag) {
+  extern __shared__ double2 dyn[];
+  int last = 0;
+  {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (int(blockIdx.x) >= probs[mid].g0) lo = mid;
+      else hi = mid - 1;
+    }
+    last = lo;
+  }
+  const int first = probs[last].slot_first;
+  for (int q = first; q <= last; ++q) {
+    const Prob& p = probs[q];
+    const int rank = int(blockIdx.x) - p.g0;
+    if (rank < 0 || rank >= p.ng + p.nh) continue;
+    run_member<VAR, ADJ>(p, rank, m_begin, m_end, hist_lo, ckpt_on, timeout, abort_flag, dyn);
+    __syncthreads();
   }
 }
 

@@ -3,7 +3,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <array>
 #include <limits>
+#include <map>
+#include <mutex>
 
 namespace fids {
 
@@ -259,7 +262,7 @@ double soe_max_rel_error(const SoeNodes& q, double gamma, double delta, double T
 // their discrete measure (e^{-s t} is nearly a low-degree polynomial in s
 // there).  The result is checked on a dense logarithmic grid and the step is
 // refined until it passes.
-int soe_build(double gamma, double delta, double T, double tol, SoeNodes& out) {
+static int soe_build_uncached(double gamma, double delta, double T, double tol, SoeNodes& out) {
   if (!(delta > 0) || !(T >= delta) || !(tol > 0) || !(gamma > 0 && gamma < 1)) return FIDS_EINVAL;
   const double eta = 0.1, d = 0.5 * double(kPiL) - eta;
   double h = 2 * double(kPiL) * d / std::log(8.0 * std::pow(std::sin(eta), -gamma) / tol);
@@ -351,6 +354,30 @@ int build_tables(const fids_params& p, HostTables& t) {
   t.chirp = make_chirp(p.n);
   t.chirp_hat = embed_conj_chirp_hat(t.chirp, t.L);
   return FIDS_OK;
+}
+
+// The node construction (quadrature, Lanczos, verification on a dense grid)
+// takes tens of milliseconds; batches and repeated set-ups ask for the same
+// (gamma, delta, T, tol) several times, so results are memoised.
+int soe_build(double gamma, double delta, double T, double tol, SoeNodes& out) {
+  static std::mutex mu;
+  static std::map<std::array<double, 4>, SoeNodes> memo;
+  const std::array<double, 4> key{gamma, delta, T, tol};
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = memo.find(key);
+    if (it != memo.end()) {
+      out = it->second;
+      return FIDS_OK;
+    }
+  }
+  const int st = soe_build_uncached(gamma, delta, T, tol, out);
+  if (st == FIDS_OK) {
+    std::lock_guard<std::mutex> g(mu);
+    if (memo.size() > 4096) memo.clear();
+    memo[key] = out;
+  }
+  return st;
 }
 
 }  // namespace fids

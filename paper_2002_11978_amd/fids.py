@@ -79,6 +79,7 @@ _SIGS = {
     "fids_batch_step": (ctypes.c_int, [_P, ctypes.POINTER(StepInfo)]),
     "fids_batch_solve_all": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(StepInfo)]),
     "fids_batch_status": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
+    "fids_batch_groups": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "fids_batch_reset": (ctypes.c_int, [_P]),
     "fids_batch_destroy": (ctypes.c_int, [_P]),
     "fids_soe_nodes": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -356,6 +357,11 @@ class Batch:
         last = (ctypes.c_int64 * self.count)()
         _check(lib().fids_batch_status(self.h, st, last), "fids_batch_status")
         return list(st), list(last)
+
+    def groups(self):
+        ng = (ctypes.c_int32 * self.count)()
+        _check(lib().fids_batch_groups(self.h, ng), "fids_batch_groups")
+        return list(ng)
 
     def reset(self):
         _check(lib().fids_batch_reset(self.h), "fids_batch_reset")

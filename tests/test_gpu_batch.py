@@ -1,9 +1,11 @@
 """GPU tests of the batched form: independent problems of (1.1) with uneven n,
 (alpha, gamma), kappa and f advanced together, one workgroup per problem.
 
-A batch member runs the same arithmetic as a single problem solved with a
-one-workgroup plan (wg_count = 1), so the two agree bit for bit; members small
-enough for the oracle are also checked against it.
+The batch gives large members a group of several workgroups and packs small
+ones into shared one-workgroup slots.  A member runs the same arithmetic as a
+single problem whose plan targets the member's group size (wg_count =
+fids_batch_groups), so the two agree bit for bit; members small enough for
+the oracle are also checked against it.
 """
 import os
 
@@ -36,8 +38,8 @@ def _batch(pbs, **kw):
                       [to_dev(pb.phi) for pb in pbs])
 
 
-def _solo(pb, **kw):
-    prob = fids.Problem(_params(pb, wg_count=1, **kw), to_dev(pb.kappa), to_dev(pb.f), to_dev(pb.phi))
+def _solo(pb, wg=1, **kw):
+    prob = fids.Problem(_params(pb, wg_count=wg, **kw), to_dev(pb.kappa), to_dev(pb.f), to_dev(pb.phi))
     uT, _, reps = prob.solve_all()
     out = uT.cpu().numpy()
     prob.close()
@@ -56,11 +58,14 @@ def _mixed_members(M):
 def test_batch_members_equal_solo_and_oracle(kw):
     pbs = _mixed_members(12)
     b = _batch(pbs, **kw)
+    groups = b.groups()
+    say(f"  groups {groups}")
+    assert max(groups) > 1          # the largest members run on several workgroups
     outs, reps = b.solve_all()
     gate = 1e-7 if kw.get("precision") == 1 else 1e-8
     for i, pb in enumerate(pbs):
         u = outs[i].cpu().numpy()
-        solo, solo_reps = _solo(pb, **kw)
+        solo, solo_reps = _solo(pb, wg=groups[i], **kw)
         assert np.array_equal(u, solo), f"member {i} differs from its solo run"
         assert [r.iters for r in reps[i]] == [r.iters for r in solo_reps]
         if pb.n <= 1000:
@@ -95,7 +100,9 @@ def test_batch_step_equals_solve_all_and_reset():
 
 
 def test_batch_graph_mode_equals_persistent():
-    pbs = _mixed_members(10)
+    # equal members: every one fits a one-workgroup slot, the launch is an
+    # ordinary one and may be captured
+    pbs = [W.seeded(1.5, 0.4, 100, 10, kappa_seed=300 + i, f_seed=400 + i) for i in range(6)]
     b = _batch(pbs, **MIXED)
     ref = [o.cpu().numpy() for o in b.solve_all()[0]]
     b.close()
@@ -104,6 +111,7 @@ def test_batch_graph_mode_equals_persistent():
         g = _batch(pbs, **MIXED)
     finally:
         del os.environ["FIDS_BATCH_MODE"]
+    assert g.groups() == [1] * len(pbs)
     for rep in range(3):           # the captured graph is replayed after each reset
         outs, _ = g.solve_all()
         for a, o in zip(ref, outs):
@@ -146,6 +154,8 @@ def test_heterogeneous_batch_full_size_sampled():
     M = 256
     pbs = [W.batch_member(p, M=M) for p in range(256)]
     b = _batch(pbs, krylov_tol=1e-10, **MIXED)
+    groups = b.groups()
+    say(f"  group sizes used: {sorted(set(groups))}, workgroups {sum(g for g in groups if g > 1)} in groups")
     try:
         outs, reps = b.solve_all()
     finally:
@@ -158,7 +168,7 @@ def test_heterogeneous_batch_full_size_sampled():
     ns = [pb.n for pb in pbs]
     sample = sorted({int(np.argmin(ns)), int(np.argmax(ns)), 17, 101, 200})
     for i in sample:
-        solo, _ = _solo(pbs[i], krylov_tol=1e-10, **MIXED)
+        solo, _ = _solo(pbs[i], wg=groups[i], krylov_tol=1e-10, **MIXED)
         assert np.array_equal(outs[i].cpu().numpy(), solo), f"member {i} (n={ns[i]})"
     its = np.mean([[r.iters for r in rr] for rr in reps])
     say(f"  mean FGMRES iterations {its:.2f}")
