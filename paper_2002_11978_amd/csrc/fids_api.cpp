@@ -197,7 +197,8 @@ int shapes_of(const fids_params& p, Shapes& sh, fids::SoeNodes* soe_out) {
   if (fids::soe_build(p.gamma, tau1, p.T, p.soe_tol, soe) != FIDS_OK) return FIDS_EINVAL;
   sh.nexp = int(soe.s.size());
   const int grp = p.wg_count > 0 ? p.wg_count : env_int("FIDS_WG", default_group(sh.Nc));
-  sh.pr = plan_shape(sh.Nc, grp, grp);
+  // column tiles default to one per workgroup; FIDS_TILES overrides (tuning)
+  sh.pr = plan_shape(sh.Nc, env_int("FIDS_TILES", grp), grp);
   sh.pc = plan_shape(sh.L, std::max(1, int((sh.L >> ((ilog2i(sh.L) + 1) / 2)) / 8)), 1 << 30);
   sh.pc.RU = 1;
   sh.pc.nrg = sh.pc.nunits;
