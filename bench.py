@@ -42,9 +42,10 @@ import numpy as np
 HBM_PEAK_GBS = 8000.0
 
 FORMS = {
-    "headline": dict(solver=1, precision=0, x0_mode=1, label="fgmres(20)-fp64-x0extrap"),
+    "headline": dict(solver=1, precision=0, x0_mode=2, label="fgmres(20)-fp64-x0quad"),
+    "linear_x0": dict(solver=1, precision=0, x0_mode=1, label="fgmres(20)-fp64-x0extrap"),
     "plain": dict(solver=0, precision=0, x0_mode=0, label="bicgstab-fp64-x0zero"),
-    "mixed": dict(solver=1, precision=1, x0_mode=1, label="fgmres(20)-fp64/fp32pc-x0extrap"),
+    "mixed": dict(solver=1, precision=1, x0_mode=2, label="fgmres(20)-fp64/fp32pc-x0quad"),
 }
 
 
@@ -56,7 +57,7 @@ def parse():
     ap.add_argument("--n", type=int, default=65535)
     ap.add_argument("--M", type=int, default=2048)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--forms", default="headline,plain,mixed")
+    ap.add_argument("--forms", default="headline,plain,mixed,linear_x0")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-levels", type=int, default=24)
     ap.add_argument("--cpu-n", type=int, default=4095)
@@ -138,7 +139,7 @@ def adjoint_leg(tol):
            "form": FORMS["headline"]["label"]}
     for name, extra in (("checkpoint_32", dict(checkpoint_every=32)), ("stored_states", dict(store_states=1))):
         prm = fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=pb.M, r=pb.r, soe_tol=1e-10,
-                                  krylov_tol=tol, krylov_maxit=500, kappa_time_dependent=0, solver=1, x0_mode=1,
+                                  krylov_tol=tol, krylov_maxit=500, kappa_time_dependent=0, solver=1, x0_mode=2,
                                   **extra)
         prob = fids.Problem(prm, k, f, phi)
         best = None
@@ -179,8 +180,8 @@ def batch_leg(tol, count):
     out = {"workload": f"{count} problems, n log-uniform in [511, 16383] (sum {sum(pb.n for pb in pbs)}), "
                        f"alpha~U(1.1,1.9), gamma~U(0.2,0.8), r=(2-gamma)/gamma, M={M}, seeded kappa(x,t), f(x,t)",
            "count": count, "M": M}
-    for name, cfg in (("fp64", dict(solver=1, precision=0, x0_mode=1, precond=2)),
-                      ("mixed", dict(solver=1, precision=1, x0_mode=1, precond=2))):
+    for name, cfg in (("fp64", dict(solver=1, precision=0, x0_mode=2, precond=2)),
+                      ("mixed", dict(solver=1, precision=1, x0_mode=2, precond=2))):
         params = [fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=M, r=pb.r, soe_tol=1e-10,
                                       krylov_tol=tol, krylov_maxit=500, **cfg) for pb in pbs]
         t0 = time.perf_counter()
@@ -202,7 +203,7 @@ def batch_leg(tol, count):
         fb = np.array([infos[i].pc_fp64_iters for i in range(count * M)])
         out[name] = {"problem_levels_per_s": count * M / best, "solve_ms": best * 1e3, "init_s": t_init,
                      "avg_iters": float(its.mean()), "levels_with_fp64_pc": int((fb > 0).sum()),
-                     "form": f"fgmres(20)-{'fp64' if cfg['precision'] == 0 else 'fp64/fp32pc'}-x0extrap-"
+                     "form": f"fgmres(20)-{'fp64' if cfg['precision'] == 0 else 'fp64/fp32pc'}-x0quad-"
                              "kappa-scaled-strang"}
         print(f"[bench] batch {name}: {count * M / best:.0f} problem-levels/s ({best * 1e3:.1f} ms), "
               f"its {its.mean():.2f}, fp64-pc levels {(fb > 0).sum()}", file=sys.stderr, flush=True)

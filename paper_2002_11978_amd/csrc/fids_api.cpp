@@ -158,13 +158,13 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   lo.kap = take(L * 8);
   lo.dsc = take(L * 8);
   lo.H1 = take(2 * L * 8);
-  lo.AU = take(2 * L * 8);
+  lo.AU = take(3 * L * 8);
   for (int i = 0; i < 10; ++i) lo.vec[i] = take(L * 8);
   const size_t C = size_t(std::max(p.checkpoint_every, 0));
   lo.hist_cap = p.store_states ? int(M + 1) : (C > 0 ? int(std::min(C, M) + 1) : 0);
   lo.uhist = lo.hist_cap ? take(size_t(lo.hist_cap) * L * 8) : 0;
   lo.nck = (!p.store_states && C > 0) ? int((M - 1) / C) : 0;
-  lo.ckpt = lo.nck ? take(size_t(lo.nck) * (ne + 4) * L * 8) : 0;
+  lo.ckpt = lo.nck ? take(size_t(lo.nck) * (ne + 6) * L * 8) : 0;
   if (p.store_states || C > 0) {
     lo.aprob = take(sizeof(Prob));
     lo.ainfo = take(M * sizeof(fids_step_info));
@@ -174,7 +174,7 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
     lo.Fbar = take(ne * L * 8);
     lo.alam = take(L * 8);
     lo.gk = take(L * 8);
-    lo.AUa = take(2 * L * 8);
+    lo.AUa = take(3 * L * 8);
   }
   const bool gm = p.solver == FIDS_FGMRES;
   lo.V = gm ? take(size_t(p.restart + 1) * L * 8) : 0;
@@ -387,18 +387,20 @@ int restore_segment(fids_problem* h, int a) {
   const size_t vb = size_t(hp.vlen) * 8;
   if (a == 1) {
     HIPCHK(hipMemsetAsync(hp.F, 0, size_t(hp.nexp) * vb, h->stream));
-    HIPCHK(hipMemsetAsync(hp.AU, 0, 2 * vb, h->stream));
+    HIPCHK(hipMemsetAsync(hp.AU, 0, 3 * vb, h->stream));
     HIPCHK(fids::launch_init_state(hp, h->dp, h->stream));
     return FIDS_OK;
   }
   const int C = hp.ckpt_every;
-  const double* ck = hp.ckpt + size_t((a - 1) / C - 1) * size_t(hp.nexp + 4) * hp.vlen;
+  const double* ck = hp.ckpt + size_t((a - 1) / C - 1) * size_t(hp.nexp + 6) * hp.vlen;
   const size_t v = size_t(hp.vlen);
   HIPCHK(hipMemcpyAsync(hp.u[(a - 1) % 3], ck, vb, hipMemcpyDeviceToDevice, h->stream));
   HIPCHK(hipMemcpyAsync(hp.u[(a + 1) % 3], ck + v, vb, hipMemcpyDeviceToDevice, h->stream));
-  HIPCHK(hipMemcpyAsync(hp.AU + size_t((a - 1) & 1) * v, ck + 2 * v, vb, hipMemcpyDeviceToDevice, h->stream));
-  HIPCHK(hipMemcpyAsync(hp.AU + size_t(a & 1) * v, ck + 3 * v, vb, hipMemcpyDeviceToDevice, h->stream));
-  HIPCHK(hipMemcpyAsync(hp.F, ck + 4 * v, size_t(hp.nexp) * vb, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(hp.u[a % 3], ck + 2 * v, vb, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(hp.AU + size_t((a - 1) % 3) * v, ck + 3 * v, vb, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(hp.AU + size_t((a + 1) % 3) * v, ck + 4 * v, vb, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(hp.AU + size_t(a % 3) * v, ck + 5 * v, vb, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(hp.F, ck + 6 * v, size_t(hp.nexp) * vb, hipMemcpyDeviceToDevice, h->stream));
   return FIDS_OK;
 }
 
@@ -1084,7 +1086,7 @@ int fids_batch_reset(fids_batch* b) {
   for (fids_problem* h : b->members) {
     HIPCHK(fids::launch_init_state(h->hp, h->dp, b->stream));
     HIPCHK(hipMemsetAsync(h->hp.F, 0, size_t(h->hp.nexp) * h->hp.vlen * 8, b->stream));
-    HIPCHK(hipMemsetAsync(h->hp.AU, 0, size_t(2) * h->hp.vlen * 8, b->stream));
+    HIPCHK(hipMemsetAsync(h->hp.AU, 0, size_t(3) * h->hp.vlen * 8, b->stream));
     HIPCHK(hipMemsetAsync(h->hp.bar, 0, 4 * sizeof(unsigned), b->stream));
     h->symbols_ready = false;
   }

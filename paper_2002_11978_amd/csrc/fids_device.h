@@ -84,12 +84,13 @@ struct Prob {
   int nh;                       // helper workgroups (0: the solver group streams F itself)
   const double* soec;           // [M+1] c_m = sum_j g w_j theta_{m,j}
   double* H1;                   // [2][vlen] sum_j g w_j e^{-s_j tau_m} F_j^{(m-1)}, slot m & 1
-  double* AU;                   // [2][vlen] A u^m of the last two levels, slot m & 1
+  double* AU;                   // [3][vlen] A u^m of the last three levels, slot m % 3
   unsigned* sync2;              // [0]: helper step completions, [64]: last completed level
   unsigned* hflag;              // [nh][64]: per-helper release flags (one 256-byte line each)
   // forward snapshots for the adjoint's segment recomputation
   int ckpt_every;               // C (0: none)
-  double* ckpt;                 // [(M-1)/C][nexp + 4][vlen]: u^{m-1}, u^{m-2}, A u^{m-1}, A u^{m-2}, F^{(m-1)}
+  double* ckpt;                 // [(M-1)/C][nexp + 6][vlen]: u^{m-1}, u^{m-2}, u^{m-3}, A u^{m-1}, A u^{m-2},
+                                //   A u^{m-3}, F^{(m-1)}
   // adjoint descriptor only (adjoint = 1): u[] holds the transposed solutions
   // y^m (lambda^m = y^m / kappa^m), F the adjoint history, uhist the forward
   // states u^m read back

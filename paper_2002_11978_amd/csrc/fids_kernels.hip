@@ -648,7 +648,8 @@ __device__ __forceinline__ int helper_loop(const Prob& p, int hr, int k0, int k1
 // with helpers h^m = H1^m + c_m (u^{m-1} - u^{m-2}); without them the solver
 // group advances F here.  kappa^m is copied tile-major.
 // Initial guess x0 = 0, or the extrapolation x0 = u^{m-1} + rho (u^{m-1} - u^{m-2}),
-// rho = tau_m / tau_{m-1} (x0_mode 1).  Then one of
+// rho = tau_m / tau_{m-1} (x0_mode 1), or the quadratic one through u^{m-3},
+// u^{m-2}, u^{m-1} (x0_mode 2, m >= 4).  Then one of
 //   fused (FGMRES, x0_mode 1, m >= 3): A x0 = (1+rho) A u^{m-1} - rho A u^{m-2} from
 //     the stored products, r0 = b - b_m' x0 - kappa .* A x0, partials (b,b),
 //     (r0,r0), column pass of P^{-1} on r0;
@@ -685,13 +686,26 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
   const double* H1m = p.H1 + size_t(m & 1) * p.vlen;
   const bool kscale = p.precond == FIDS_STRANG_K;
   const double kb = kscale ? p.kbar[m] : 0.0;
-  const double* Au1 = p.AU + size_t((m - 1) & 1) * p.vlen;
-  double* Au2 = p.AU + size_t(m & 1) * p.vlen;   // A u^{m-2} in, A x0 out
+  // A u^k of the last three levels: AU[k % 3]
+  const double* Au1 = p.AU + size_t((m - 1) % 3) * p.vlen;
+  const double* Au2 = p.AU + size_t((m + 1) % 3) * p.vlen;
+  double* Au3 = p.AU + size_t(m % 3) * p.vlen;   // A u^{m-3} in, A x0 out
+  // quadratic extrapolation through t_{m-3}, t_{m-2}, t_{m-1} (Lagrange
+  // weights at t_m in the step sizes h1 = tau_m, h2 = tau_{m-1}, h3 = tau_{m-2})
+  const bool quad = p.x0_mode == 2 && m >= 4;
+  double c1 = 0.0, c2 = 0.0, c3 = 0.0;
+  if (quad) {
+    const double h1 = p.tau[m], h2 = p.tau[m - 1], h3 = p.tau[m - 2];
+    c1 = (h1 + h2) * (h1 + h2 + h3) / (h2 * (h2 + h3));
+    c2 = -h1 * (h1 + h2 + h3) / (h2 * h3);
+    c3 = h1 * (h1 + h2) / ((h2 + h3) * h3);
+  }
   const int blk = 2 * pl.CT * pl.N1;
   // snapshot of the state entering level m = kC + 1 (k >= 1), taken while it
-  // streams through this phase
+  // streams through this phase: u^{m-1}, u^{m-2}, u^{m-3}, A u^{m-1}, A u^{m-2},
+  // A u^{m-3}, F^{(m-1)}
   const bool snap = ctl.ckpt_on && p.ckpt != nullptr && m >= 2 && (m - 1) % p.ckpt_every == 0;
-  double* ck = snap ? p.ckpt + size_t((m - 1) / p.ckpt_every - 1) * size_t(nexp + 4) * p.vlen : nullptr;
+  double* ck = snap ? p.ckpt + size_t((m - 1) / p.ckpt_every - 1) * size_t(nexp + 6) * p.vlen : nullptr;
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
     double acc[2] = {0.0, 0.0};
@@ -709,11 +723,12 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
           if (snap) {
             st2(ck, off, a1);
             st2(ck + p.vlen, off, a2);
+            st2(ck + 2 * size_t(p.vlen), off, ld2(x, off));
           }
           d = make_double2(a1.x - a2.x, a1.y - a2.y);
           if (self_soe) {
             double* Fp = p.F + size_t(tile) * nexp * blk + 2 * idx;
-            double* Fc = snap ? ck + size_t(4) * p.vlen + size_t(tile) * nexp * blk + 2 * idx : nullptr;
+            double* Fc = snap ? ck + size_t(6) * p.vlen + size_t(tile) * nexp * blk + 2 * idx : nullptr;
             for (int j = 0; j < nexp; ++j) {
               double2 fj = ld2(Fp, j * blk);
               if (snap) st2(Fc, j * blk, fj);
@@ -735,15 +750,22 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
         const double2 fv = nat2(fm, i0, p.n);
         const double2 kk = nat2(km, i0, p.n);
         b = mask2(make_double2(bm * a1.x - h.x + fv.x, bm * a1.y - h.y + fv.y), i0, p.n);
-        if (warm) x0 = mask2(make_double2(a1.x + rho * d.x, a1.y + rho * d.y), i0, p.n);
+        if (quad) {
+          const double2 a2 = ld2(um2, off), a3 = ld2(x, off);
+          x0 = mask2(make_double2(c1 * a1.x + c2 * a2.x + c3 * a3.x, c1 * a1.y + c2 * a2.y + c3 * a3.y), i0, p.n);
+        } else if (warm) {
+          x0 = mask2(make_double2(a1.x + rho * d.x, a1.y + rho * d.y), i0, p.n);
+        }
         if (fused) {
-          const double2 A1 = ld2(Au1, off), A2 = ld2(Au2, off);
+          const double2 A1 = ld2(Au1, off), A2 = ld2(Au2, off), A3 = ld2(Au3, off);
           if (snap) {
-            st2(ck + 2 * size_t(p.vlen), off, A1);
-            st2(ck + 3 * size_t(p.vlen), off, A2);
+            st2(ck + 3 * size_t(p.vlen), off, A1);
+            st2(ck + 4 * size_t(p.vlen), off, A2);
+            st2(ck + 5 * size_t(p.vlen), off, A3);
           }
-          const double2 ax = make_double2((1.0 + rho) * A1.x - rho * A2.x, (1.0 + rho) * A1.y - rho * A2.y);
-          st2(Au2, off, mask2(ax, i0, p.n));
+          const double2 ax = quad ? make_double2(c1 * A1.x + c2 * A2.x + c3 * A3.x, c1 * A1.y + c2 * A2.y + c3 * A3.y)
+                                  : make_double2((1.0 + rho) * A1.x - rho * A2.x, (1.0 + rho) * A1.y - rho * A2.y);
+          st2(Au3, off, mask2(ax, i0, p.n));
           r0 = mask2(make_double2(b.x - (bm * x0.x + kk.x * ax.x), b.y - (bm * x0.y + kk.y * ax.y)), i0, p.n);
         }
         st2(p.kap, off, kk);
@@ -788,7 +810,7 @@ __device__ __forceinline__ void phase_r0(const Prob& p, int m, int rank, const L
   const double inv = 1.0 / double(pl.Nc);
   const double bm = p.beta[m];
   const double* x = p.u[m % 3];
-  double* Aum = p.AU + size_t(m & 1) * p.vlen;   // A x is kept as A u^m
+  double* Aum = p.AU + size_t(m % 3) * p.vlen;   // A x is kept as A u^m
   const bool bicg = p.solver == FIDS_BICGSTAB;
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
@@ -1513,6 +1535,14 @@ __device__ __forceinline__ void phase_pc_col64(const Prob& p, int rank, const Ld
   }
 }
 
+// Counters a level carries from one restart cycle to the next.
+struct Cyc {
+  double rr;          // ||r||^2 of the true residual in VR
+  int it, mv, floor_hits, it64;
+  bool est_conv;
+};
+constexpr int kFallback = 1;   // internal: continue the level with the FP64 preconditioner
+
 // Restart cycles of flexible GMRES(J) with the preconditioner in precision RP,
 // from the true residual r (VR, ||r||^2 = rr) whose P^{-1} column pass is in
 // pT<RP>.  With the FP32 preconditioner, a level still unconverged after its
@@ -1522,8 +1552,10 @@ __device__ __forceinline__ void phase_pc_col64(const Prob& p, int rank, const Ld
 // than about 1e5.
 template <typename RP>
 __device__ __forceinline__ int fgmres_cycles(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L, const Hess& H,
-                                             double bnorm, double rr, int it, int mv, int floor_hits,
-                                             bool est_conv, int it64) {
+                                             double bnorm, Cyc& c) {
+  double rr = c.rr;
+  int it = c.it, mv = c.mv, floor_hits = c.floor_hits, it64 = c.it64;
+  bool est_conv = c.est_conv;
   const RP* Q = pQ<RP>(p, m);
   const double tol = p.tol;
   const int J = p.restart;
@@ -1543,9 +1575,8 @@ __device__ __forceinline__ int fgmres_cycles(const Prob& p, int m, int rank, Ctl
     if (it >= p.maxit) { write_info(p, rank, m, it, mv, beta0 / bnorm, FIDS_ENOCONV, it64); return FIDS_ENOCONV; }
     if constexpr (sizeof(RP) == 4) {
       if (p.qhat != nullptr && p.zd != nullptr && it >= J) {
-        phase_pc_col64(p, rank, L);
-        BARRIER();
-        return fgmres_cycles<double>(p, m, rank, ctl, L, H, bnorm, rr, it, mv, floor_hits, est_conv, 0);
+        c.rr = rr; c.it = it; c.mv = mv; c.floor_hits = floor_hits; c.it64 = 0; c.est_conv = est_conv;
+        return kFallback;
       }
     }
     const int it_cycle0 = it;
@@ -1643,7 +1674,17 @@ __device__ __forceinline__ int level_fgmres(const Prob& p, int m, int rank, Ctl&
     if (st != FIDS_OK) return st;
   }
   if (bad(bb) || bad(rr)) { write_info(p, rank, m, 0, 0, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
-  return fgmres_cycles<RP>(p, m, rank, ctl, L, H, sqrt(bb), rr, 0, (p.x0_mode != 0) ? 1 : 0, 0, false, 0);
+  Cyc c{rr, 0, (p.x0_mode != 0) ? 1 : 0, 0, 0, false};
+  const int st = fgmres_cycles<RP>(p, m, rank, ctl, L, H, sqrt(bb), c);
+  if constexpr (sizeof(RP) == 4) {
+    if (st == kFallback) {
+      // the FP32 cycles' state is dead here, so the FP64 cycles reuse its registers
+      phase_pc_col64(p, rank, L);
+      BARRIER();
+      return fgmres_cycles<double>(p, m, rank, ctl, L, H, sqrt(bb), c);
+    }
+  }
+  return st;
 }
 
 // Level solver variants; each kernel instance holds one, so that its register
