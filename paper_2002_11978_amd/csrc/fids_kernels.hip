@@ -863,9 +863,11 @@ __device__ __forceinline__ void adj_grad_item(const Prob& p, int mg, int i0, int
 }
 
 // Right-hand side of adjoint level m: b = kappa^m .* ubar^m, initial guess 0 or
-// the extrapolation y^{m+1} + rho (y^{m+1} - y^{m+2}), rho = tau_{m+1}/tau_{m+2};
-// then the column pass of A on x0 (warm) or of P^{-1} on b (cold).  First the
-// pending gradient of level m+1 (column pass C of A u^{m+1}).
+// the extrapolation y^{m+1} + rho (y^{m+1} - y^{m+2}), rho = tau_{m+1}/tau_{m+2}
+// (x0_mode 1), or the quadratic one through y^{m+3}, y^{m+2}, y^{m+1}
+// (x0_mode 2, m + 3 <= M); then the column pass of A on x0 (warm) or of P^{-1}
+// on b (cold).  First the pending gradient of level m+1 (column pass C of
+// A u^{m+1}).
 template <typename RP>
 __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, const Lds& L, const Ctl& ctl) {
   const Plan& pl = L.pl;
@@ -877,6 +879,15 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
   const double* y2 = p.u[(m + 2) % 3];
   double* x = p.u[m % 3];
   const double rho = (m + 2 <= p.M) ? p.tau[m + 1] / p.tau[m + 2] : 0.0;
+  // backward in time: step sizes h1 = tau_{m+1}, h2 = tau_{m+2}, h3 = tau_{m+3}
+  const bool quad = p.x0_mode == 2 && m + 3 <= p.M;
+  double c1 = 0.0, c2 = 0.0, c3 = 0.0;
+  if (quad) {
+    const double h1 = p.tau[m + 1], h2 = p.tau[m + 2], h3 = p.tau[m + 3];
+    c1 = (h1 + h2) * (h1 + h2 + h3) / (h2 * (h2 + h3));
+    c2 = -h1 * (h1 + h2 + h3) / (h2 * h3);
+    c3 = h1 * (h1 + h2) / ((h2 + h3) * h3);
+  }
   const double* km = p.kappa + (p.kappa_td ? size_t(m - 1) * p.n : 0);
   const bool kscale = p.precond == FIDS_STRANG_K;
   const double kb = kscale ? p.kbar[m] : 0.0;
@@ -894,7 +905,10 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
         const double2 kk = nat2(km, i0, p.n);
         const double2 u = ld2(ub, off);
         b = mask2(make_double2(kk.x * u.x, kk.y * u.y), i0, p.n);
-        if (warm) {
+        if (quad) {
+          const double2 a1 = ld2(y1, off), a2 = ld2(y2, off), a3 = ld2(x, off);   // x holds y^{m+3}
+          x0 = mask2(make_double2(c1 * a1.x + c2 * a2.x + c3 * a3.x, c1 * a1.y + c2 * a2.y + c3 * a3.y), i0, p.n);
+        } else if (warm) {
           const double2 a1 = ld2(y1, off), a2 = ld2(y2, off);
           x0 = mask2(make_double2(a1.x + rho * (a1.x - a2.x), a1.y + rho * (a1.y - a2.y)), i0, p.n);
         }
