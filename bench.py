@@ -44,6 +44,7 @@ HBM_PEAK_GBS = 8000.0
 FORMS = {
     "headline": dict(solver=1, precision=0, x0_mode=2, label="fgmres(20)-fp64-x0quad"),
     "linear_x0": dict(solver=1, precision=0, x0_mode=1, label="fgmres(20)-fp64-x0extrap"),
+    "cubic_x0": dict(solver=1, precision=0, x0_mode=3, label="fgmres(20)-fp64-x0cubic"),
     "plain": dict(solver=0, precision=0, x0_mode=0, label="bicgstab-fp64-x0zero"),
     "mixed": dict(solver=1, precision=1, x0_mode=2, label="fgmres(20)-fp64/fp32pc-x0quad"),
 }

@@ -98,10 +98,10 @@ typedef struct fids_params {
     int32_t precision;    /* FIDS_FP64 | FIDS_MIXED (MIXED needs FIDS_FGMRES)      */
     int32_t precond;      /* FIDS_STRANG | FIDS_NONE | FIDS_STRANG_K               */
     int32_t kappa_time_dependent; /* 1: kappa_d is [M][n]; 0: kappa_d is [n]      */
-    int32_t x0_mode;      /* 0: zero initial guess (Sec. 5); 1: linear             */
-                          /* extrapolation from u^{m-2}, u^{m-1} on the graded     */
-                          /* mesh; 2: quadratic extrapolation from u^{m-3},        */
-                          /* u^{m-2}, u^{m-1} (linear at m = 2, 3)                 */
+    int32_t x0_mode;      /* 0: zero initial guess (Sec. 5); k = 1, 2, 3:          */
+                          /* polynomial extrapolation of degree k on the graded    */
+                          /* mesh through u^{m-1}, ..., u^{m-1-k} (lower degree    */
+                          /* where fewer levels exist)                             */
     int32_t store_states; /* 1: keep every u^m in the workspace (fids_adjoint     */
                           /* then needs no recomputation); 0: keep only what       */
                           /* stepping needs                                        */

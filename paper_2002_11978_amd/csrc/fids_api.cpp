@@ -82,9 +82,9 @@ struct Layout {
   size_t tw1r, tw1rf, tw2r, tw2rf, tw1c, tw1cf, tw2c, tw2cf, twlo, twlof, twhi, twhif;
   size_t qhat, qhatf;
   size_t Tb, q, Tq;
-  size_t u[3], F, kap, dsc, vec[10], uhist, T, Tf, tau, V, Z, Zf, soec, H1, AU, sync2, hflag;
+  size_t u[fids::kRing], F, kap, dsc, vec[10], uhist, T, Tf, tau, V, Z, Zf, soec, H1, AU, sync2, hflag;
   // adjoint: segment snapshots and the adjoint descriptor's state
-  size_t ckpt, aprob, ainfo, astatus, ubar[3], yr[3], Fbar, alam, gk, AUa;
+  size_t ckpt, aprob, ainfo, astatus, ubar[3], yr[fids::kRing], Fbar, alam, gk, AUa;
   int nck;          // snapshots held (levels kC + 1, k = 1..nck)
   int hist_cap;     // states uhist holds
   size_t total;
@@ -153,28 +153,28 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   lo.Tb = take(size_t(lo.chunk) * L * 16);
   lo.q = take(size_t(lo.chunk) * n * 8);
   lo.Tq = take(size_t(lo.chunk) * Nc * 16);
-  for (int i = 0; i < 3; ++i) lo.u[i] = take(L * 8);
+  for (int i = 0; i < fids::kRing; ++i) lo.u[i] = take(L * 8);
   lo.F = take(ne * L * 8);
   lo.kap = take(L * 8);
   lo.dsc = take(L * 8);
   lo.H1 = take(2 * L * 8);
-  lo.AU = take(3 * L * 8);
+  lo.AU = take(size_t(fids::kRing) * L * 8);
   for (int i = 0; i < 10; ++i) lo.vec[i] = take(L * 8);
   const size_t C = size_t(std::max(p.checkpoint_every, 0));
   lo.hist_cap = p.store_states ? int(M + 1) : (C > 0 ? int(std::min(C, M) + 1) : 0);
   lo.uhist = lo.hist_cap ? take(size_t(lo.hist_cap) * L * 8) : 0;
   lo.nck = (!p.store_states && C > 0) ? int((M - 1) / C) : 0;
-  lo.ckpt = lo.nck ? take(size_t(lo.nck) * (ne + 6) * L * 8) : 0;
+  lo.ckpt = lo.nck ? take(size_t(lo.nck) * (ne + 2 * fids::kRing) * L * 8) : 0;
   if (p.store_states || C > 0) {
     lo.aprob = take(sizeof(Prob));
     lo.ainfo = take(M * sizeof(fids_step_info));
     lo.astatus = take(4 * sizeof(int));
     for (int i = 0; i < 3; ++i) lo.ubar[i] = take(L * 8);
-    for (int i = 0; i < 3; ++i) lo.yr[i] = take(L * 8);
+    for (int i = 0; i < fids::kRing; ++i) lo.yr[i] = take(L * 8);
     lo.Fbar = take(ne * L * 8);
     lo.alam = take(L * 8);
     lo.gk = take(L * 8);
-    lo.AUa = take(3 * L * 8);
+    lo.AUa = take(size_t(fids::kRing) * L * 8);
   }
   const bool gm = p.solver == FIDS_FGMRES;
   lo.V = gm ? take(size_t(p.restart + 1) * L * 8) : 0;
@@ -387,20 +387,21 @@ int restore_segment(fids_problem* h, int a) {
   const size_t vb = size_t(hp.vlen) * 8;
   if (a == 1) {
     HIPCHK(hipMemsetAsync(hp.F, 0, size_t(hp.nexp) * vb, h->stream));
-    HIPCHK(hipMemsetAsync(hp.AU, 0, 3 * vb, h->stream));
+    HIPCHK(hipMemsetAsync(hp.AU, 0, size_t(fids::kRing) * vb, h->stream));
     HIPCHK(fids::launch_init_state(hp, h->dp, h->stream));
     return FIDS_OK;
   }
   const int C = hp.ckpt_every;
-  const double* ck = hp.ckpt + size_t((a - 1) / C - 1) * size_t(hp.nexp + 6) * hp.vlen;
+  constexpr int R = fids::kRing;
+  const double* ck = hp.ckpt + size_t((a - 1) / C - 1) * size_t(hp.nexp + 2 * R) * hp.vlen;
   const size_t v = size_t(hp.vlen);
-  HIPCHK(hipMemcpyAsync(hp.u[(a - 1) % 3], ck, vb, hipMemcpyDeviceToDevice, h->stream));
-  HIPCHK(hipMemcpyAsync(hp.u[(a + 1) % 3], ck + v, vb, hipMemcpyDeviceToDevice, h->stream));
-  HIPCHK(hipMemcpyAsync(hp.u[a % 3], ck + 2 * v, vb, hipMemcpyDeviceToDevice, h->stream));
-  HIPCHK(hipMemcpyAsync(hp.AU + size_t((a - 1) % 3) * v, ck + 3 * v, vb, hipMemcpyDeviceToDevice, h->stream));
-  HIPCHK(hipMemcpyAsync(hp.AU + size_t((a + 1) % 3) * v, ck + 4 * v, vb, hipMemcpyDeviceToDevice, h->stream));
-  HIPCHK(hipMemcpyAsync(hp.AU + size_t(a % 3) * v, ck + 5 * v, vb, hipMemcpyDeviceToDevice, h->stream));
-  HIPCHK(hipMemcpyAsync(hp.F, ck + 6 * v, size_t(hp.nexp) * vb, hipMemcpyDeviceToDevice, h->stream));
+  for (int k = 0; k < R; ++k) {
+    const int slot = (a - 1 - k + 2 * R) % R;    // u^{a-1-k}, A u^{a-1-k}
+    HIPCHK(hipMemcpyAsync(hp.u[slot], ck + size_t(k) * v, vb, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(hp.AU + size_t(slot) * v, ck + size_t(R + k) * v, vb, hipMemcpyDeviceToDevice,
+                          h->stream));
+  }
+  HIPCHK(hipMemcpyAsync(hp.F, ck + size_t(2 * R) * v, size_t(hp.nexp) * vb, hipMemcpyDeviceToDevice, h->stream));
   return FIDS_OK;
 }
 
@@ -484,7 +485,7 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   hp.qhat = lo.qhat ? at<double>(ws, lo.qhat) : nullptr;
   hp.qhatf = lo.qhatf ? at<float>(ws, lo.qhatf) : nullptr;
   hp.kappa = kappa_d; hp.f = f_d; hp.phi = phi_d;
-  for (int i = 0; i < 3; ++i) hp.u[i] = at<double>(ws, lo.u[i]);
+  for (int i = 0; i < fids::kRing; ++i) hp.u[i] = at<double>(ws, lo.u[i]);
   hp.F = at<double>(ws, lo.F); hp.kap = at<double>(ws, lo.kap); hp.dsc = at<double>(ws, lo.dsc);
   hp.kbar = at<double>(ws, lo.kbar);
   for (int i = 0; i < 10; ++i) hp.vec[i] = at<double>(ws, lo.vec[i]);
@@ -548,7 +549,7 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
     ha.nh = 0;
     ha.f = nullptr;
     ha.ckpt = nullptr;
-    for (int i = 0; i < 3; ++i) ha.u[i] = at<double>(ws, lo.yr[i]);
+    for (int i = 0; i < fids::kRing; ++i) ha.u[i] = at<double>(ws, lo.yr[i]);
     for (int i = 0; i < 3; ++i) ha.ubar[i] = at<double>(ws, lo.ubar[i]);
     ha.F = at<double>(ws, lo.Fbar);
     ha.lam = at<double>(ws, lo.alam);
@@ -797,7 +798,7 @@ int fids_step(fids_problem* h, double* u_out_d, fids_step_info* info) {
   if (info) *info = tmp[size_t(m - 1)];
   if (st != FIDS_OK) return st;
   if (u_out_d) {
-    HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.u[m % 3], u_out_d, h->stream));
+    HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.u[m % fids::kRing], u_out_d, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
   }
   return FIDS_OK;
@@ -809,7 +810,7 @@ int fids_solve_all(fids_problem* h, double* uT_d, double* u_all_d, fids_step_inf
   if (h->level >= h->sh.M) return FIDS_ESTATE;
   const int st = run_levels(h, h->sh.M, per_step);
   if (st != FIDS_OK) return st;
-  if (uT_d) HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.u[h->sh.M % 3], uT_d, h->stream));
+  if (uT_d) HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.u[h->sh.M % fids::kRing], uT_d, h->stream));
   if (u_all_d)
     for (int64_t m = 0; m <= h->sh.M; ++m)
       HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.uhist + size_t(m) * h->hp.vlen,
@@ -829,10 +830,8 @@ int fids_adjoint(fids_problem* h, const double* dJ_duT_d, double* g_kappa_d, dou
   ha.g_kappa = (ha.kappa_td && g_kappa_d) ? g_kappa_d : nullptr;
   ha.g_f = g_f_d;
   HIPCHK(hipMemcpyAsync(h->dpa, &ha, sizeof(Prob), hipMemcpyHostToDevice, h->stream));
-  for (int i = 0; i < 3; ++i) {
-    HIPCHK(hipMemsetAsync(ha.ubar[i], 0, vb, h->stream));
-    HIPCHK(hipMemsetAsync(ha.u[i], 0, vb, h->stream));
-  }
+  for (int i = 0; i < 3; ++i) HIPCHK(hipMemsetAsync(ha.ubar[i], 0, vb, h->stream));
+  for (int i = 0; i < fids::kRing; ++i) HIPCHK(hipMemsetAsync(ha.u[i], 0, vb, h->stream));
   HIPCHK(hipMemsetAsync(ha.F, 0, size_t(ha.nexp) * vb, h->stream));
   HIPCHK(hipMemsetAsync(ha.gk, 0, vb, h->stream));
   HIPCHK(hipMemsetAsync(ha.lam, 0, vb, h->stream));
@@ -1057,7 +1056,7 @@ int fids_batch_solve_all(fids_batch* b, double* const* uT_d, fids_step_info* inf
     for (int32_t i = 0; i < b->count; ++i) {
       if (!uT_d[i]) continue;
       const fids_problem* h = b->members[size_t(i)];
-      HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.u[M % 3], uT_d[i], b->stream));
+      HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.u[M % fids::kRing], uT_d[i], b->stream));
     }
     HIPCHK(hipStreamSynchronize(b->stream));
   }
@@ -1086,7 +1085,7 @@ int fids_batch_reset(fids_batch* b) {
   for (fids_problem* h : b->members) {
     HIPCHK(fids::launch_init_state(h->hp, h->dp, b->stream));
     HIPCHK(hipMemsetAsync(h->hp.F, 0, size_t(h->hp.nexp) * h->hp.vlen * 8, b->stream));
-    HIPCHK(hipMemsetAsync(h->hp.AU, 0, size_t(3) * h->hp.vlen * 8, b->stream));
+    HIPCHK(hipMemsetAsync(h->hp.AU, 0, size_t(fids::kRing) * h->hp.vlen * 8, b->stream));
     HIPCHK(hipMemsetAsync(h->hp.bar, 0, 4 * sizeof(unsigned), b->stream));
     h->symbols_ready = false;
   }

@@ -17,6 +17,7 @@ namespace fids {
 constexpr int kThreads = 512;     // threads per workgroup in every kernel
 constexpr int kMaxFFT = 4096;     // longest per-workgroup FFT (complex points)
 constexpr int kMaxRestart = 32;
+constexpr int kRing = 4;          // states kept: u^m lives in u[m % kRing] (and A u^m in AU)
 
 // Partial-sum slots (one value per column tile each).
 enum Slot {
@@ -64,7 +65,7 @@ struct Prob {
   const double* f;
   const double* phi;
   // state (tile-major, vlen doubles each)
-  double* u[3];                 // u^m lives in u[m % 3]
+  double* u[kRing];             // u^m lives in u[m % kRing]
   double* F;                    // [ntiles][nexp][2*CT*N1]
   double* kap;                  // kappa^m, tile-major
   double* dsc;                  // kbar_m / kappa^m, tile-major (kappa-scaled preconditioner)
@@ -84,13 +85,13 @@ struct Prob {
   int nh;                       // helper workgroups (0: the solver group streams F itself)
   const double* soec;           // [M+1] c_m = sum_j g w_j theta_{m,j}
   double* H1;                   // [2][vlen] sum_j g w_j e^{-s_j tau_m} F_j^{(m-1)}, slot m & 1
-  double* AU;                   // [3][vlen] A u^m of the last three levels, slot m % 3
+  double* AU;                   // [kRing][vlen] A u^k of the last levels, slot k % kRing
   unsigned* sync2;              // [0]: helper step completions, [64]: last completed level
   unsigned* hflag;              // [nh][64]: per-helper release flags (one 256-byte line each)
   // forward snapshots for the adjoint's segment recomputation
   int ckpt_every;               // C (0: none)
-  double* ckpt;                 // [(M-1)/C][nexp + 6][vlen]: u^{m-1}, u^{m-2}, u^{m-3}, A u^{m-1}, A u^{m-2},
-                                //   A u^{m-3}, F^{(m-1)}
+  double* ckpt;                 // [(M-1)/C][nexp + 2 kRing][vlen]: u^{m-1..m-kRing}, A u^{m-1..m-kRing},
+                                //   F^{(m-1)}
   // adjoint descriptor only (adjoint = 1): u[] holds the transposed solutions
   // y^m (lambda^m = y^m / kappa^m), F the adjoint history, uhist the forward
   // states u^m read back

@@ -611,8 +611,8 @@ __device__ __forceinline__ int helper_loop(const Prob& p, int hr, int k0, int k1
       dn[j] = next ? p.gw[j] * p.decay[size_t(k + 1) * nexp + j] : 0.0;
     }
     __syncthreads();
-    const double* um1 = p.u[(k - 1) % 3];
-    const double* um2 = p.u[(k + 1) % 3];
+    const double* um1 = p.u[(k - 1) % kRing];
+    const double* um2 = p.u[(k - 2 + kRing) % kRing];
     double* H = p.H1 + size_t((k + 1) & 1) * p.vlen;
     for (int q = q0 + threadIdx.x; q < q1; q += kThreads) {
       const int tile = (2 * q) / blk, lp = (2 * q) % blk;
@@ -643,15 +643,30 @@ __device__ __forceinline__ int helper_loop(const Prob& p, int hr, int k0, int k1
   return FIDS_OK;
 }
 
+// Lagrange weights at t of polynomial extrapolation through npts earlier
+// levels at distances d_k = t - t_k > 0 (k = 1..npts, nearest first):
+// w_k = prod_{j != k} d_j / (d_j - d_k).
+__device__ __forceinline__ void extrap_weights(const double* d, int npts, double* w) {
+  for (int k = 0; k < kRing; ++k) {
+    double v = 0.0;
+    if (k < npts) {
+      v = 1.0;
+      for (int j = 0; j < npts; ++j)
+        if (j != k) v *= d[j] / (d[j] - d[k]);
+    }
+    w[k] = v;
+  }
+}
+
 // Right-hand side of level m (eq. 3.16gu with the SOE history):
 //   b = b_m' u^{m-1} - h^m + f^m,  h^m = sum_j g w_j F_j^{(m)};
 // with helpers h^m = H1^m + c_m (u^{m-1} - u^{m-2}); without them the solver
 // group advances F here.  kappa^m is copied tile-major.
-// Initial guess x0 = 0, or the extrapolation x0 = u^{m-1} + rho (u^{m-1} - u^{m-2}),
-// rho = tau_m / tau_{m-1} (x0_mode 1), or the quadratic one through u^{m-3},
-// u^{m-2}, u^{m-1} (x0_mode 2, m >= 4).  Then one of
-//   fused (FGMRES, x0_mode 1, m >= 3): A x0 = (1+rho) A u^{m-1} - rho A u^{m-2} from
-//     the stored products, r0 = b - b_m' x0 - kappa .* A x0, partials (b,b),
+// Initial guess x0 = 0, or polynomial extrapolation on the graded mesh through
+// the last x0_mode + 1 states (linear, quadratic, cubic; fewer near m = 1).
+// Then one of
+//   fused (FGMRES, x0_mode >= 1, m >= 3): A x0 = sum_k w_k A u^{m-k} from the
+//     stored products, r0 = b - b_m' x0 - kappa .* A x0, partials (b,b),
 //     (r0,r0), column pass of P^{-1} on r0;
 //   warm: column pass of A on x0 (the residual follows after the row pass);
 //   cold: r0 = b (BiCGSTAB also r^ = p = b), column pass of P^{-1} on b.
@@ -678,34 +693,32 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
   const double rho = (m >= 2) ? p.tau[m] / p.tau[m - 1] : 0.0;
   const bool warm = p.x0_mode != 0;
   const bool bicg = p.solver == FIDS_BICGSTAB;
-  const double* um1 = p.u[(m - 1) % 3];
-  const double* um2 = p.u[(m + 1) % 3];  // (m-2) mod 3
-  double* x = p.u[m % 3];
+  const double* um1 = p.u[(m - 1) % kRing];
+  const double* um2 = p.u[(m - 2 + kRing) % kRing];
+  double* x = p.u[m % kRing];              // holds u^{m-kRing} until x0 is stored
   const double* fm = p.f + size_t(m - 1) * p.n;
   const double* km = p.kappa + (p.kappa_td ? size_t(m - 1) * p.n : 0);
   const double* H1m = p.H1 + size_t(m & 1) * p.vlen;
   const bool kscale = p.precond == FIDS_STRANG_K;
   const double kb = kscale ? p.kbar[m] : 0.0;
-  // A u^k of the last three levels: AU[k % 3]
-  const double* Au1 = p.AU + size_t((m - 1) % 3) * p.vlen;
-  const double* Au2 = p.AU + size_t((m + 1) % 3) * p.vlen;
-  double* Au3 = p.AU + size_t(m % 3) * p.vlen;   // A u^{m-3} in, A x0 out
-  // quadratic extrapolation through t_{m-3}, t_{m-2}, t_{m-1} (Lagrange
-  // weights at t_m in the step sizes h1 = tau_m, h2 = tau_{m-1}, h3 = tau_{m-2})
-  const bool quad = p.x0_mode == 2 && m >= 4;
-  double c1 = 0.0, c2 = 0.0, c3 = 0.0;
-  if (quad) {
-    const double h1 = p.tau[m], h2 = p.tau[m - 1], h3 = p.tau[m - 2];
-    c1 = (h1 + h2) * (h1 + h2 + h3) / (h2 * (h2 + h3));
-    c2 = -h1 * (h1 + h2 + h3) / (h2 * h3);
-    c3 = h1 * (h1 + h2) / ((h2 + h3) * h3);
+  // extrapolation: npts earlier states u^{m-1}, ..., u^{m-npts} with weights w[]
+  // (the fused residual also needs their stored A u^{m-k}, kept from level 1 on)
+  const int npts = !warm ? 0 : min(p.x0_mode + 1, fused ? m - 1 : m);
+  double w[kRing];
+  {
+    double d[kRing];
+    double acc_t = 0.0;
+    for (int k = 0; k < kRing; ++k) {
+      acc_t += (m - k >= 1) ? p.tau[m - k] : 0.0;
+      d[k] = acc_t;                        // t_m - t_{m-1-k}
+    }
+    extrap_weights(d, npts, w);
   }
   const int blk = 2 * pl.CT * pl.N1;
   // snapshot of the state entering level m = kC + 1 (k >= 1), taken while it
-  // streams through this phase: u^{m-1}, u^{m-2}, u^{m-3}, A u^{m-1}, A u^{m-2},
-  // A u^{m-3}, F^{(m-1)}
+  // streams through this phase: u^{m-1..m-kRing}, A u^{m-1..m-kRing}, F^{(m-1)}
   const bool snap = ctl.ckpt_on && p.ckpt != nullptr && m >= 2 && (m - 1) % p.ckpt_every == 0;
-  double* ck = snap ? p.ckpt + size_t((m - 1) / p.ckpt_every - 1) * size_t(nexp + 6) * p.vlen : nullptr;
+  double* ck = snap ? p.ckpt + size_t((m - 1) / p.ckpt_every - 1) * size_t(nexp + 2 * kRing) * p.vlen : nullptr;
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
     double acc[2] = {0.0, 0.0};
@@ -720,15 +733,15 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
         double2 d = make_double2(0.0, 0.0);
         if (m >= 2) {
           const double2 a2 = ld2(um2, off);
-          if (snap) {
-            st2(ck, off, a1);
-            st2(ck + p.vlen, off, a2);
-            st2(ck + 2 * size_t(p.vlen), off, ld2(x, off));
-          }
+          if (snap)
+            for (int k = 0; k < kRing; ++k) {
+              st2(ck + size_t(k) * p.vlen, off, ld2(p.u[(m - 1 - k + 2 * kRing) % kRing], off));
+              if (fused) st2(ck + size_t(kRing + k) * p.vlen, off, ld2(p.AU + size_t((m - 1 - k + 2 * kRing) % kRing) * p.vlen, off));
+            }
           d = make_double2(a1.x - a2.x, a1.y - a2.y);
           if (self_soe) {
             double* Fp = p.F + size_t(tile) * nexp * blk + 2 * idx;
-            double* Fc = snap ? ck + size_t(6) * p.vlen + size_t(tile) * nexp * blk + 2 * idx : nullptr;
+            double* Fc = snap ? ck + size_t(2 * kRing) * p.vlen + size_t(tile) * nexp * blk + 2 * idx : nullptr;
             for (int j = 0; j < nexp; ++j) {
               double2 fj = ld2(Fp, j * blk);
               if (snap) st2(Fc, j * blk, fj);
@@ -750,22 +763,31 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
         const double2 fv = nat2(fm, i0, p.n);
         const double2 kk = nat2(km, i0, p.n);
         b = mask2(make_double2(bm * a1.x - h.x + fv.x, bm * a1.y - h.y + fv.y), i0, p.n);
-        if (quad) {
-          const double2 a2 = ld2(um2, off), a3 = ld2(x, off);
-          x0 = mask2(make_double2(c1 * a1.x + c2 * a2.x + c3 * a3.x, c1 * a1.y + c2 * a2.y + c3 * a3.y), i0, p.n);
-        } else if (warm) {
+        if (npts == 2) {
           x0 = mask2(make_double2(a1.x + rho * d.x, a1.y + rho * d.y), i0, p.n);
+        } else if (npts > 0) {
+          x0 = make_double2(0.0, 0.0);
+          for (int k = 0; k < npts; ++k) {
+            const double2 uk = ld2(p.u[(m - 1 - k + 2 * kRing) % kRing], off);
+            x0.x += w[k] * uk.x;
+            x0.y += w[k] * uk.y;
+          }
+          x0 = mask2(x0, i0, p.n);
         }
         if (fused) {
-          const double2 A1 = ld2(Au1, off), A2 = ld2(Au2, off), A3 = ld2(Au3, off);
-          if (snap) {
-            st2(ck + 3 * size_t(p.vlen), off, A1);
-            st2(ck + 4 * size_t(p.vlen), off, A2);
-            st2(ck + 5 * size_t(p.vlen), off, A3);
+          double2 ax = make_double2(0.0, 0.0);
+          if (npts == 2) {
+            const double2 A1 = ld2(p.AU + size_t((m - 1) % kRing) * p.vlen, off);
+            const double2 A2 = ld2(p.AU + size_t((m - 2 + kRing) % kRing) * p.vlen, off);
+            ax = make_double2((1.0 + rho) * A1.x - rho * A2.x, (1.0 + rho) * A1.y - rho * A2.y);
+          } else {
+            for (int k = 0; k < npts; ++k) {
+              const double2 Ak = ld2(p.AU + size_t((m - 1 - k + 2 * kRing) % kRing) * p.vlen, off);
+              ax.x += w[k] * Ak.x;
+              ax.y += w[k] * Ak.y;
+            }
           }
-          const double2 ax = quad ? make_double2(c1 * A1.x + c2 * A2.x + c3 * A3.x, c1 * A1.y + c2 * A2.y + c3 * A3.y)
-                                  : make_double2((1.0 + rho) * A1.x - rho * A2.x, (1.0 + rho) * A1.y - rho * A2.y);
-          st2(Au3, off, mask2(ax, i0, p.n));
+          st2(p.AU + size_t(m % kRing) * p.vlen, off, mask2(ax, i0, p.n));
           r0 = mask2(make_double2(b.x - (bm * x0.x + kk.x * ax.x), b.y - (bm * x0.y + kk.y * ax.y)), i0, p.n);
         }
         st2(p.kap, off, kk);
@@ -809,8 +831,8 @@ __device__ __forceinline__ void phase_r0(const Prob& p, int m, int rank, const L
   const Plan& pl = L.pl;
   const double inv = 1.0 / double(pl.Nc);
   const double bm = p.beta[m];
-  const double* x = p.u[m % 3];
-  double* Aum = p.AU + size_t(m % 3) * p.vlen;   // A x is kept as A u^m
+  const double* x = p.u[m % kRing];
+  double* Aum = p.AU + size_t(m % kRing) * p.vlen;   // A x is kept as A u^m
   const bool bicg = p.solver == FIDS_BICGSTAB;
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
@@ -875,18 +897,21 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
   const bool warm = p.x0_mode != 0;
   const bool bicg = p.solver == FIDS_BICGSTAB;
   const double* ub = p.ubar[m % 3];
-  const double* y1 = p.u[(m + 1) % 3];
-  const double* y2 = p.u[(m + 2) % 3];
-  double* x = p.u[m % 3];
+  const double* y1 = p.u[(m + 1) % kRing];
+  const double* y2 = p.u[(m + 2) % kRing];
+  double* x = p.u[m % kRing];
   const double rho = (m + 2 <= p.M) ? p.tau[m + 1] / p.tau[m + 2] : 0.0;
-  // backward in time: step sizes h1 = tau_{m+1}, h2 = tau_{m+2}, h3 = tau_{m+3}
-  const bool quad = p.x0_mode == 2 && m + 3 <= p.M;
-  double c1 = 0.0, c2 = 0.0, c3 = 0.0;
-  if (quad) {
-    const double h1 = p.tau[m + 1], h2 = p.tau[m + 2], h3 = p.tau[m + 3];
-    c1 = (h1 + h2) * (h1 + h2 + h3) / (h2 * (h2 + h3));
-    c2 = -h1 * (h1 + h2 + h3) / (h2 * h3);
-    c3 = h1 * (h1 + h2) / ((h2 + h3) * h3);
+  // backward in time: y^{m+1}, ..., y^{m+npts} at distances t_{m+k} - t_m
+  const int npts = !warm ? 0 : min(p.x0_mode + 1, p.M - m);
+  double w[kRing];
+  {
+    double d[kRing];
+    double acc_t = 0.0;
+    for (int k = 0; k < kRing; ++k) {
+      acc_t += (m + 1 + k <= p.M) ? p.tau[m + 1 + k] : 0.0;
+      d[k] = acc_t;
+    }
+    extrap_weights(d, npts, w);
   }
   const double* km = p.kappa + (p.kappa_td ? size_t(m - 1) * p.n : 0);
   const bool kscale = p.precond == FIDS_STRANG_K;
@@ -905,12 +930,16 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
         const double2 kk = nat2(km, i0, p.n);
         const double2 u = ld2(ub, off);
         b = mask2(make_double2(kk.x * u.x, kk.y * u.y), i0, p.n);
-        if (quad) {
-          const double2 a1 = ld2(y1, off), a2 = ld2(y2, off), a3 = ld2(x, off);   // x holds y^{m+3}
-          x0 = mask2(make_double2(c1 * a1.x + c2 * a2.x + c3 * a3.x, c1 * a1.y + c2 * a2.y + c3 * a3.y), i0, p.n);
-        } else if (warm) {
+        if (npts == 2) {
           const double2 a1 = ld2(y1, off), a2 = ld2(y2, off);
           x0 = mask2(make_double2(a1.x + rho * (a1.x - a2.x), a1.y + rho * (a1.y - a2.y)), i0, p.n);
+        } else if (npts > 0) {
+          for (int k = 0; k < npts; ++k) {
+            const double2 yk = ld2(p.u[(m + 1 + k) % kRing], off);   // y^{m+kRing} sits in x
+            x0.x += w[k] * yk.x;
+            x0.y += w[k] * yk.y;
+          }
+          x0 = mask2(x0, i0, p.n);
         }
         st2(p.kap, off, kk);
         if (kscale) st2(p.dsc, off, mask2(make_double2(kb / kk.x, kb / kk.y), i0, p.n));
@@ -933,7 +962,7 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
   }
 }
 
-// After the solve of adjoint level m (y^m in u[m % 3]):
+// After the solve of adjoint level m (y^m in u[m % kRing]):
 //   lambda = y / kappa^m;  dJ/df^m = lambda;  ubar^{m-1} += b_m' lambda;
 // the history recurrence in reverse (m >= 2; F^{(1)} = 0 has no inputs):
 //   Fbar_j -= g w_j lambda;  rho = sum_j theta_{m,j} Fbar_j;  Fbar_j *= e^{-s_j tau_m};
@@ -953,7 +982,7 @@ __device__ __forceinline__ void phase_adj_post(const Prob& p, int m, int rank, c
   }
   __syncthreads();
   const double bm = p.beta[m];
-  const double* y = p.u[m % 3];
+  const double* y = p.u[m % kRing];
   double* u1 = p.ubar[(m - 1) % 3];
   double* u2 = p.ubar[(m + 1) % 3];   // (m-2) mod 3
   const double* um = p.uhist + size_t(m - ctl.hist_lo) * p.vlen;
@@ -1112,7 +1141,7 @@ __device__ __forceinline__ void bi_s(const Prob& p, int rank, double alpha, cons
 __device__ __forceinline__ void bi_update(const Prob& p, int m, int rank, double alpha, double omega, double beta,
                                           const Lds& L) {
   const Plan& pl = L.pl;
-  double* x = p.u[m % 3];
+  double* x = p.u[m % kRing];
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
     double acc[1] = {0.0};
@@ -1147,7 +1176,7 @@ __device__ __forceinline__ void bi_update(const Prob& p, int m, int rank, double
 // x += alpha p^ (half-iteration exit).
 __device__ __forceinline__ void bi_half(const Prob& p, int m, int rank, double alpha) {
   const Plan& pl = p.pl;   // sizes only
-  double* x = p.u[m % 3];
+  double* x = p.u[m % kRing];
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
     for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
@@ -1510,7 +1539,7 @@ __device__ __forceinline__ void gm_P3(const Prob& p, int rank, int j, double eta
 template <typename RP>
 __device__ __forceinline__ void gm_F1(const Prob& p, int m, int rank, int jl, const Lds& L, const Hess& H) {
   const Plan& pl = L.pl;
-  double* x = p.u[m % 3];
+  double* x = p.u[m % kRing];
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
     for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
@@ -1809,7 +1838,7 @@ __device__ __forceinline__ void run_member(const Prob& p, int rank, int m_begin,
   }
   // keep u^{m_end} with the stored states (tile-local copy, no barrier needed)
   if (hist_lo >= 0) {
-    const double* ue = p.u[m_end % 3];
+    const double* ue = p.u[m_end % kRing];
     double* dst = p.uhist + size_t(m_end - hist_lo) * p.vlen;
     for (int tile = rank; tile < L.pl.ntiles; tile += p.ng) {
       const TileIdx t = tile_idx(L.pl, tile);
@@ -1864,7 +1893,7 @@ __global__ void __launch_bounds__(kThreads) k_init_state(const Prob* pp) {
     const int off = t.toff + 2 * idx;
     const double2 v = nat2(p.phi, i0, p.n);
     st2(p.u[0], off, v);
-    st2(p.u[2], off, v);   // u^{-1} := u^0 (level 1 extrapolates to u^0; unused otherwise)
+    st2(p.u[kRing - 1], off, v);   // u^{-1} := u^0 (never weighted: extrapolation uses levels >= 0)
     if (p.store_states) st2(p.uhist, off, v);
   }
 }

@@ -27,7 +27,7 @@ int validate(const fids_params& p) {
   if (p.precision != FIDS_FP64 && p.precision != FIDS_MIXED) return FIDS_EINVAL;
   if (p.precision == FIDS_MIXED && p.solver != FIDS_FGMRES) return FIDS_EINVAL;
   if (p.precond != FIDS_STRANG && p.precond != FIDS_NONE && p.precond != FIDS_STRANG_K) return FIDS_EINVAL;
-  if (p.x0_mode < 0 || p.x0_mode > 2) return FIDS_EINVAL;
+  if (p.x0_mode < 0 || p.x0_mode > 3) return FIDS_EINVAL;
   if (p.wg_count < 0 || p.wg_count > 4096) return FIDS_EINVAL;
   if (p.soe_helpers < -1 || p.soe_helpers > 4096) return FIDS_EINVAL;
   if (p.checkpoint_every < 0) return FIDS_EINVAL;

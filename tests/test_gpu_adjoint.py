@@ -95,7 +95,8 @@ def test_adjoint_matches_oracle(n, M, td, kw):
 
 
 @pytest.mark.parametrize("kw", [VARIANTS[0], VARIANTS[3], VARIANTS[4],
-                                pytest.param(dict(solver=1, precision=0, x0_mode=2), id="fgmres-fp64-x0quad")])
+                                pytest.param(dict(solver=1, precision=0, x0_mode=2), id="fgmres-fp64-x0quad"),
+                                pytest.param(dict(solver=1, precision=0, x0_mode=3), id="fgmres-fp64-x0cubic")])
 @pytest.mark.parametrize("C", [1, 3, 5, 16, 40])
 def test_checkpointed_equals_stored_states(C, kw):
     """Segments recomputed from snapshots give the stored-states gradients
@@ -112,7 +113,7 @@ def test_checkpoint_snapshots_do_not_change_the_forward():
     pb = W.seeded(1.5, 0.4, 1023, 20, kappa_seed=31, f_seed=32)
     outs = []
     for kw in (dict(), dict(checkpoint_every=3), dict(store_states=1)):
-        p = _params(pb, solver=1, x0_mode=2, **kw)
+        p = _params(pb, solver=1, x0_mode=3, **kw)
         prob = fids.Problem(p, to_dev(pb.kappa), to_dev(pb.f), to_dev(pb.phi))
         uT, _, _ = prob.solve_all()
         outs.append(uT.cpu().numpy())

@@ -34,6 +34,8 @@ VARIANTS = [
     pytest.param(dict(solver=0, precision=0, x0_mode=2), id="bicgstab-fp64-x0quad"),
     pytest.param(dict(solver=1, precision=0, x0_mode=2), id="fgmres-fp64-x0quad"),
     pytest.param(dict(solver=1, precision=1, x0_mode=2, precond=2), id="fgmres-mixed-x0quad-kpc"),
+    pytest.param(dict(solver=0, precision=0, x0_mode=3), id="bicgstab-fp64-x0cubic"),
+    pytest.param(dict(solver=1, precision=0, x0_mode=3), id="fgmres-fp64-x0cubic"),
 ]
 
 
