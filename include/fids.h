@@ -245,6 +245,14 @@ int fids_batch_status(const fids_batch* b, int32_t* status, int64_t* last_level)
  * slots that run their members one after another. */
 int fids_batch_groups(const fids_batch* b, int32_t* ng);
 
+/* Host-only: the placement fids_batch_init would choose on `resident`
+ * co-resident workgroups.  ng[i] is member i's group size and slot[i] its
+ * slot (members of a one-workgroup slot run in turn); *makespan (may be NULL)
+ * is the modelled cost of the slowest slot, in units of one level of a
+ * length-1 embedding on one workgroup. */
+int fids_batch_plan(const fids_params* p, int32_t count, int32_t resident, int32_t* ng, int32_t* slot,
+                    double* makespan);
+
 /* Back to level 0 for every member (per-level symbols rebuilt on the next call). */
 int fids_batch_reset(fids_batch* b);
 int fids_batch_destroy(fids_batch* b);

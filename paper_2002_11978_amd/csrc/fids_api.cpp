@@ -651,6 +651,34 @@ std::vector<Slot> schedule_batch(const std::vector<double>& c, const std::vector
   return out;
 }
 
+// Per-member cost (embedding length L), largest useful group (powers of two,
+// at least 1024 packed points per workgroup, at most 64) and, optionally, a
+// bound on the level kernel's LDS (one-workgroup plans have the largest tiles)
+// with a descriptor for the occupancy query.
+int batch_costs(const fids_params* p, int32_t count, std::vector<double>& cost, std::vector<int>& kmax,
+                size_t* lds_bound, Prob* probe) {
+  cost.assign(size_t(count), 0.0);
+  kmax.assign(size_t(count), 1);
+  for (int32_t i = 0; i < count; ++i) {
+    fids_params q = p[i];
+    batch_params(q, 1);
+    Shapes sh;
+    if (shapes_of(q, sh, nullptr) != FIDS_OK) return FIDS_EINVAL;
+    cost[size_t(i)] = double(sh.L);
+    int k = 1;
+    while (k * 2 <= std::min(64, sh.pr.N2) && int64_t(k) * 2 * 1024 <= sh.Nc) k *= 2;
+    kmax[size_t(i)] = k;
+    if (lds_bound && probe) {
+      probe->nexp = sh.nexp; probe->L = int(sh.L); probe->precision = q.precision; probe->solver = q.solver;
+      probe->pl.CT = sh.pr.CT; probe->pl.N1 = sh.pr.N1; probe->pl.N2 = sh.pr.N2; probe->pl.RU = sh.pr.RU;
+      const int tws = (ilog2i(sh.L) + 1) / 2;
+      probe->pl.twshift = tws; probe->pl.twmask = (1 << tws) - 1;
+      *lds_bound = std::max(*lds_bound, fids::level_lds_bytes(*probe));
+    }
+  }
+  return FIDS_OK;
+}
+
 int batch_layout(const fids_params* p, int32_t count, BatchLayout& bl) {
   const int64_t M = p[0].M;
   size_t off = 0;
@@ -912,25 +940,11 @@ int fids_batch_init(const fids_params* p, int32_t count, const double* const* ka
   b->dinfo = at<fids_step_info>(b->ws, bl.info);
   b->dabort = at<int>(b->ws, bl.abort_);
   // costs, largest groups and an LDS bound (one-workgroup plans have the largest tiles)
-  std::vector<double> cost(static_cast<size_t>(count));
-  std::vector<int> kmax(static_cast<size_t>(count));
+  std::vector<double> cost;
+  std::vector<int> kmax;
   size_t lds_bound = 0;
   Prob probe{};
-  for (int32_t i = 0; i < count; ++i) {
-    fids_params q = p[i];
-    batch_params(q, 1);
-    Shapes sh;
-    if (shapes_of(q, sh, nullptr) != FIDS_OK) return fail(FIDS_EINVAL);
-    cost[size_t(i)] = double(sh.L);
-    int k = 1;
-    while (k * 2 <= std::min(64, sh.pr.N2) && int64_t(k) * 2 * 1024 <= sh.Nc) k *= 2;
-    kmax[size_t(i)] = k;
-    probe.nexp = sh.nexp; probe.L = int(sh.L); probe.precision = q.precision; probe.solver = q.solver;
-    probe.pl.CT = sh.pr.CT; probe.pl.N1 = sh.pr.N1; probe.pl.N2 = sh.pr.N2; probe.pl.RU = sh.pr.RU;
-    const int tws = (ilog2i(sh.L) + 1) / 2;
-    probe.pl.twshift = tws; probe.pl.twmask = (1 << tws) - 1;
-    lds_bound = std::max(lds_bound, fids::level_lds_bytes(probe));
-  }
+  if (batch_costs(p, count, cost, kmax, &lds_bound, &probe) != FIDS_OK) return fail(FIDS_EINVAL);
   int resident = count;
   {
     int dev = 0, cus = 0, per_cu = 0;
@@ -1077,6 +1091,27 @@ int fids_batch_status(const fids_batch* b, int32_t* status, int64_t* last_level)
 int fids_batch_groups(const fids_batch* b, int32_t* ng) {
   if (!b || !ng) return FIDS_EINVAL;
   for (int32_t i = 0; i < b->count; ++i) ng[i] = b->groups[size_t(i)];
+  return FIDS_OK;
+}
+
+int fids_batch_plan(const fids_params* p, int32_t count, int32_t resident, int32_t* ng, int32_t* slot,
+                    double* makespan) {
+  if (!p || count < 1 || resident < 1 || !ng || !slot) return FIDS_EINVAL;
+  std::vector<double> cost;
+  std::vector<int> kmax;
+  if (batch_costs(p, count, cost, kmax, nullptr, nullptr) != FIDS_OK) return FIDS_EINVAL;
+  const std::vector<Slot> slots = schedule_batch(cost, kmax, resident);
+  double worst = 0.0;
+  for (size_t k = 0; k < slots.size(); ++k) {
+    double load = 0.0;
+    for (int i : slots[k].members) {
+      ng[i] = slots[k].ng;
+      slot[i] = int32_t(k);
+      load += group_cost(cost[size_t(i)], slots[k].ng);
+    }
+    worst = std::max(worst, load);
+  }
+  if (makespan) *makespan = worst;
   return FIDS_OK;
 }
 

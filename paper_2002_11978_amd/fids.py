@@ -80,6 +80,9 @@ _SIGS = {
     "fids_batch_solve_all": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(StepInfo)]),
     "fids_batch_status": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
     "fids_batch_groups": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "fids_batch_plan": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_double)]),
     "fids_batch_reset": (ctypes.c_int, [_P]),
     "fids_batch_destroy": (ctypes.c_int, [_P]),
     "fids_soe_nodes": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -175,6 +178,17 @@ def strang_eigs(n, alpha, l=1.0, mu=0.0):
     out = np.zeros(n)
     _check(lib().fids_strang_eigs(n, alpha, l, mu, _dptr(out)), "fids_strang_eigs")
     return out
+
+
+def batch_plan(params, resident):
+    """(group sizes, slots, modelled makespan) of a batch on `resident` workgroups (host only)."""
+    count = len(params)
+    arr = (Params * count)(*params)
+    ng = (ctypes.c_int32 * count)()
+    slot = (ctypes.c_int32 * count)()
+    mk = ctypes.c_double(0.0)
+    _check(lib().fids_batch_plan(arr, count, resident, ng, slot, ctypes.byref(mk)), "fids_batch_plan")
+    return list(ng), list(slot), mk.value
 
 
 def level_coefficients(gamma, T, M, r):

@@ -111,3 +111,53 @@ def test_single_hip_runtime_in_process():
             "print(len({l.split()[-1] for l in maps.splitlines() if 'libamdhip64' in l}))")
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, check=True)
     assert out.stdout.strip() == "1"
+
+
+def _batch_params(count=256, M=256):
+    from paper_2002_11978_amd import workloads as W
+    return [fids.default_params(alpha=a, gamma=g, n=n, M=M, r=(2 - g) / g)
+            for n, a, g in W.batch_shapes(count)]
+
+
+def _embed(n):
+    L = 4
+    while L < 2 * n:
+        L *= 2
+    return L
+
+
+@pytest.mark.parametrize("resident", [1, 7, 64, 256, 1024])
+def test_batch_plan_is_a_valid_placement(resident):
+    """Every member is placed once; groups of more than one workgroup hold one
+    member; the workgroups used fit `resident`; the modelled makespan is at
+    least the obvious lower bounds and within 1.5x of the larger one."""
+    ps = _batch_params()
+    ng, slot, mk = fids.batch_plan(ps, resident)
+    slots = {}
+    for i, s in enumerate(slot):
+        slots.setdefault(s, []).append(i)
+    used = 0
+    for s, members in slots.items():
+        sizes = {ng[i] for i in members}
+        assert len(sizes) == 1
+        k = sizes.pop()
+        if k > 1:
+            assert len(members) == 1
+        used += k
+    assert used <= max(resident, 1)
+    cost = [_embed(p.n) for p in ps]
+    if resident >= 2:
+        assert mk >= sum(cost) / resident - 1e-9
+    assert mk >= max(c / 64 for c in cost)
+    if resident >= 64:
+        lower = max(sum(cost) / resident, max(min(c / k + (260 + 12 * k if k > 1 else 0)
+                                                  for k in (1, 2, 4, 8, 16, 32, 64) if k * 1024 <= c // 2 or k == 1)
+                                              for c in cost))
+        assert mk <= 1.5 * lower
+
+
+def test_batch_plan_single_workgroup_packs_everything():
+    ps = _batch_params(12)
+    ng, slot, mk = fids.batch_plan(ps, 1)
+    assert ng == [1] * 12 and len(set(slot)) == 1
+    assert mk == pytest.approx(sum(_embed(p.n) for p in ps))
