@@ -36,12 +36,15 @@ struct PlanShape {
 
 constexpr int kTileCap = 2048;
 
-PlanShape plan_shape(int64_t Nc, int target_tiles, int target_groups) {
+PlanShape plan_shape(int64_t Nc, int target_tiles, int target_groups, int skew = 0) {
   PlanShape s{};
   const int p = ilog2i(Nc);
   s.Nc = int(Nc);
-  s.log1 = (p + 1) / 2;
-  s.log2 = p / 2;
+  // skew > 0 moves factors of two from the column length N1 to the row length
+  // N2: more columns per tile for the same tile count, i.e. longer contiguous
+  // runs (CT complex values) in the column passes' strided accesses
+  s.log1 = std::max(1, (p + 1) / 2 - std::max(skew, 0));
+  s.log2 = p - s.log1;
   s.N1 = 1 << s.log1;
   s.N2 = 1 << s.log2;
   int nt = 1;
@@ -198,11 +201,13 @@ int shapes_of(const fids_params& p, Shapes& sh, fids::SoeNodes* soe_out) {
   sh.nexp = int(soe.s.size());
   const int grp = p.wg_count > 0 ? p.wg_count : env_int("FIDS_WG", default_group(sh.Nc));
   // column tiles default to one per workgroup; FIDS_TILES overrides (tuning)
-  sh.pr = plan_shape(sh.Nc, env_int("FIDS_TILES", grp), grp);
+  const int skew = env_int("FIDS_SKEW", 0);
+  sh.pr = plan_shape(sh.Nc, env_int("FIDS_TILES", grp), grp, skew);
   sh.pc = plan_shape(sh.L, std::max(1, int((sh.L >> ((ilog2i(sh.L) + 1) / 2)) / 8)), 1 << 30);
   sh.pc.RU = 1;
   sh.pc.nrg = sh.pc.nunits;
-  sh.ps = plan_shape(sh.Nc, std::max(1, int((sh.Nc >> ((ilog2i(sh.Nc) + 1) / 2)) / 8)), 1 << 30);
+  // the symbol plan shares the level plan's N1 / N2 twiddle tables: same split
+  sh.ps = plan_shape(sh.Nc, std::max(1, int((sh.Nc >> ((ilog2i(sh.Nc) + 1) / 2)) / 8)), 1 << 30, skew);
   sh.ps.RU = 1;
   sh.ps.nrg = sh.ps.nunits;
   if (soe_out) *soe_out = soe;
