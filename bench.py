@@ -189,6 +189,9 @@ def batch_leg(tol, count):
         t0 = time.perf_counter()
         b = fids.Batch(params, *arrs)
         t_init = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        b.tune(levels=4)
+        t_tune = time.perf_counter() - t0
         infos = (fids.StepInfo * (count * M))()
         best = None
         for _ in range(3):
@@ -204,6 +207,7 @@ def batch_leg(tol, count):
         its = np.array([infos[i].iters for i in range(count * M)])
         fb = np.array([infos[i].pc_fp64_iters for i in range(count * M)])
         out[name] = {"problem_levels_per_s": count * M / best, "solve_ms": best * 1e3, "init_s": t_init,
+                     "tune_s": t_tune,
                      "avg_iters": float(its.mean()), "levels_with_fp64_pc": int((fb > 0).sum()),
                      "form": f"fgmres(20)-{'fp64' if cfg['precision'] == 0 else 'fp64/fp32pc'}-x0cubic-"
                              "kappa-scaled-strang"}
@@ -339,6 +343,7 @@ def main():
     nexp = int(fids.soe_nodes(pb.gamma, (1.0 / pb.M) ** pb.r, 1.0, 1e-10)[0].size)
     forms = [f for f in args.forms.split(",") if f]
     res = {}
+    finals = {}
     ref_uT = None
     for form in forms:
         run = Runner(pb, form, args.tol, dev)
@@ -353,6 +358,7 @@ def main():
         rr = np.array([run.infos[i].relres for i in range(pb.M)])
         nbytes = float(sum(level_bytes(form, pb.n, nexp, int(it[i]), int(mv[i])) for i in range(pb.M)))
         uT, _ = run.final_state()
+        finals[form] = uT
         if ref_uT is None:
             ref_uT = uT
         res[form] = dict(value=steps / wall, ms_per_step=wall * 1e3 / steps, event_ms=ev_ms,
@@ -394,6 +400,10 @@ def main():
         out["roofline"]["traffic_source"] = os.path.relpath(TRAFFIC_FILE, os.path.dirname(KERNEL_SRC) + "/../..")
     if "plain" in res:
         out["speedup_vs_plain_fp64"] = head["value"] / res["plain"]["value"]
+        pl = finals["plain"]
+        for f in res:
+            res[f]["uT_rel_diff_vs_plain_fp64"] = float(np.max(np.abs(finals[f] - pl)) / np.max(np.abs(pl)))
+        out["forms"] = {f: {k: v for k, v in r.items()} for f, r in res.items()}
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(args.tol)
         out["adj_fwd_ratio"] = out["adjoint"]["adj_over_fwd"]

@@ -253,6 +253,14 @@ int fids_batch_groups(const fids_batch* b, int32_t* ng);
 int fids_batch_plan(const fids_params* p, int32_t count, int32_t resident, int32_t* ng, int32_t* slot,
                     double* makespan);
 
+/* Autotuner: for every class of members with the same embedding length and
+ * group size, times `levels` levels of one member with each candidate
+ * column/row tiling (tile counts 1x, 2x, 4x the group, 2048- or 4096-point
+ * LDS tiles, within the device's LDS) and gives the whole class the fastest.
+ * Needs the batch at level 0; leaves it reset to level 0.  tile_ct (may be
+ * NULL) receives each member's chosen columns per tile. */
+int fids_batch_tune(fids_batch* b, int32_t levels, int32_t* tile_ct);
+
 /* Back to level 0 for every member (per-level symbols rebuilt on the next call). */
 int fids_batch_reset(fids_batch* b);
 int fids_batch_destroy(fids_batch* b);

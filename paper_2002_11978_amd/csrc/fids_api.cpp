@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -36,7 +37,7 @@ struct PlanShape {
 
 constexpr int kTileCap = 2048;
 
-PlanShape plan_shape(int64_t Nc, int target_tiles, int target_groups, int skew = 0) {
+PlanShape plan_shape(int64_t Nc, int target_tiles, int target_groups, int skew = 0, int cap = kTileCap) {
   PlanShape s{};
   const int p = ilog2i(Nc);
   s.Nc = int(Nc);
@@ -50,14 +51,14 @@ PlanShape plan_shape(int64_t Nc, int target_tiles, int target_groups, int skew =
   int nt = 1;
   while (nt * 2 <= std::min(target_tiles, s.N2)) nt *= 2;   // powers of two only
   int ct = s.N2 / nt;
-  while (ct > 1 && ct * s.N1 > kTileCap) ct >>= 1;
+  while (ct > 1 && ct * s.N1 > cap) ct >>= 1;
   s.CT = ct;
   s.ntiles = s.N2 / s.CT;
   s.nunits = s.N1 / 2;
   int ng = 1;
   while (ng * 2 <= std::min(target_groups, s.nunits)) ng *= 2;
   int ru = s.nunits / ng;
-  while (ru > 1 && 2 * ru * s.N2 > kTileCap) ru >>= 1;
+  while (ru > 1 && 2 * ru * s.N2 > cap) ru >>= 1;
   s.RU = ru;
   s.nrg = s.nunits / s.RU;
   return s;
@@ -1118,6 +1119,105 @@ int fids_batch_plan(const fids_params* p, int32_t count, int32_t resident, int32
   }
   if (makespan) *makespan = worst;
   return FIDS_OK;
+}
+
+int fids_batch_tune(fids_batch* b, int32_t levels, int32_t* tile_ct) {
+  if (!b || levels < 1) return FIDS_EINVAL;
+  if (b->level != 0 || b->poisoned) return FIDS_ESTATE;
+  const int lv = int(std::min<int64_t>(levels, b->M));
+  int dev = 0, max_lds = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+  {
+    const int sst = batch_symbols(b);
+    if (sst != FIDS_OK) return sst;
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  // classes of members with equal embedding length and group size
+  std::map<std::pair<int, int>, std::vector<int>> classes;
+  for (int32_t i = 0; i < b->count; ++i) classes[{b->members[size_t(i)]->hp.L, b->groups[size_t(i)]}].push_back(i);
+  int st = FIDS_OK;
+  for (auto& kv : classes) {
+    const int ng = kv.first.second;
+    fids_problem* rep_h = b->members[size_t(kv.second.front())];
+    const Prob keep = rep_h->hp;
+    const PlanShape base = rep_h->sh.pr;
+    struct Cand { PlanShape ps; size_t lds; float ms; };
+    std::vector<Cand> cands;
+    for (int cap : {kTileCap, 2 * kTileCap})
+      for (int mul : {1, 2, 4}) {
+        PlanShape ps = plan_shape(base.Nc, ng * mul, ng, 0, cap);
+        if (ps.N1 != base.N1 || ps.N2 != base.N2) continue;
+        Prob trial = keep;
+        trial.pl.CT = ps.CT; trial.pl.ntiles = ps.ntiles; trial.pl.RU = ps.RU; trial.pl.nrg = ps.nrg;
+        const size_t lds = fids::level_lds_bytes(trial);
+        if (lds + 4096 > size_t(max_lds)) continue;   // room for the kernel's static LDS
+        bool dup = false;
+        for (const Cand& c : cands) dup |= (c.ps.CT == ps.CT && c.ps.RU == ps.RU);
+        if (!dup) cands.push_back({ps, lds, 0.f});
+      }
+    for (Cand& c : cands) {
+      // the representative alone, from level 0, on its group
+      Prob trial = keep;
+      trial.pl.CT = c.ps.CT; trial.pl.ntiles = c.ps.ntiles; trial.pl.RU = c.ps.RU; trial.pl.nrg = c.ps.nrg;
+      trial.g0 = 0;
+      trial.slot_first = 0;
+      trial.status = keep.status;
+      HIPCHK(hipMemcpyAsync(rep_h->dp, &trial, sizeof(Prob), hipMemcpyHostToDevice, b->stream));
+      HIPCHK(fids::launch_init_state(trial, rep_h->dp, b->stream));
+      HIPCHK(hipMemsetAsync(trial.F, 0, size_t(trial.nexp) * trial.vlen * 8, b->stream));
+      HIPCHK(hipMemsetAsync(trial.AU, 0, size_t(fids::kRing) * trial.vlen * 8, b->stream));
+      HIPCHK(hipMemsetAsync(trial.bar, 0, 4 * sizeof(unsigned), b->stream));
+      if (c.lds > 65536) HIPCHK(fids::set_level_lds_limit(trial, c.lds));
+      HIPCHK(hipEventRecord(e0, b->stream));
+      if (ng > 1) {
+        HIPCHK(hipMemsetAsync(b->dabort, 0, sizeof(int), b->stream));
+        HIPCHK(fids::launch_levels(trial, rep_h->dp, 1, ng, c.lds, 1, lv, -1, 0, b->timeout_ticks, b->dabort,
+                                   b->stream));
+      } else {
+        HIPCHK(fids::launch_levels_plain(trial, rep_h->dp, 1, 1, c.lds, 1, lv, b->stream));
+      }
+      HIPCHK(hipEventRecord(e1, b->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      HIPCHK(hipEventElapsedTime(&c.ms, e0, e1));
+      int w[2] = {0, 0};
+      HIPCHK(hipMemcpy(w, keep.status, sizeof(w), hipMemcpyDeviceToHost));
+      if (w[0] != FIDS_OK) { st = w[0]; c.ms = 1e30f; }
+    }
+    size_t best = 0;
+    for (size_t k = 1; k < cands.size(); ++k)
+      if (cands[k].ms < cands[best].ms) best = k;
+    for (int i : kv.second) {
+      fids_problem* h = b->members[size_t(i)];
+      h->hp.pl.CT = cands[best].ps.CT; h->hp.pl.ntiles = cands[best].ps.ntiles;
+      h->hp.pl.RU = cands[best].ps.RU; h->hp.pl.nrg = cands[best].ps.nrg;
+      h->lds = cands[best].lds;
+      if (tile_ct) tile_ct[i] = cands[best].ps.CT;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // descriptors in launch order, member copies, LDS limit
+  b->lds = 0;
+  for (size_t d = 0; d < b->hprobs.size(); ++d) {
+    for (fids_problem* h : b->members) {
+      if (h->hp.status == b->hprobs[d].status) {
+        b->hprobs[d].pl = h->hp.pl;
+        break;
+      }
+    }
+  }
+  for (fids_problem* h : b->members) {
+    b->lds = std::max(b->lds, h->lds);
+    HIPCHK(hipMemcpyAsync(h->dp, &h->hp, sizeof(Prob), hipMemcpyHostToDevice, b->stream));
+  }
+  if (b->lds > 65536) HIPCHK(fids::set_level_lds_limit(b->hprobs[0], b->lds));
+  HIPCHK(hipMemcpyAsync(b->dprobs, b->hprobs.data(), b->hprobs.size() * sizeof(Prob), hipMemcpyHostToDevice,
+                        b->stream));
+  const int rs = fids_batch_reset(b);
+  return st != FIDS_OK ? st : rs;
 }
 
 int fids_batch_reset(fids_batch* b) {

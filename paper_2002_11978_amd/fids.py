@@ -80,6 +80,7 @@ _SIGS = {
     "fids_batch_solve_all": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(StepInfo)]),
     "fids_batch_status": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
     "fids_batch_groups": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "fids_batch_tune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "fids_batch_plan": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_double)]),
@@ -371,6 +372,12 @@ class Batch:
         last = (ctypes.c_int64 * self.count)()
         _check(lib().fids_batch_status(self.h, st, last), "fids_batch_status")
         return list(st), list(last)
+
+    def tune(self, levels=4):
+        """Autotune the tile shapes per class of members; returns each member's columns per tile."""
+        ct = (ctypes.c_int32 * self.count)()
+        _check(lib().fids_batch_tune(self.h, levels, ct), "fids_batch_tune")
+        return list(ct)
 
     def groups(self):
         ng = (ctypes.c_int32 * self.count)()

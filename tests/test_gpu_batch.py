@@ -173,3 +173,27 @@ def test_heterogeneous_batch_full_size_sampled():
     its = np.mean([[r.iters for r in rr] for rr in reps])
     say(f"  mean FGMRES iterations {its:.2f}")
     b.close()
+
+
+def test_batch_tune_keeps_results():
+    """The autotuner may change every class's tiling; results stay within
+    rounding of the untuned batch and match the oracle; a tuned batch is
+    deterministic."""
+    pbs = _mixed_members(10)
+    b = _batch(pbs, solver=1, precision=0, x0_mode=3)
+    ref = [o.cpu().numpy() for o in b.solve_all()[0]]
+    b.reset()
+    ct = b.tune(levels=3)
+    say(f"  tuned columns per tile {ct}")
+    assert all(c >= 1 for c in ct)
+    outs1 = [o.cpu().numpy() for o in b.solve_all()[0]]
+    b.reset()
+    outs2 = [o.cpu().numpy() for o in b.solve_all()[0]]
+    for a, c, d in zip(ref, outs1, outs2):
+        assert np.array_equal(c, d)
+        assert rel_maxnorm(c, a) <= 1e-10
+    for i, pb in enumerate(pbs):
+        if pb.n <= 1000:
+            R = oracle.dids_solve(pb.alpha, pb.gamma, pb.n, pb.M, pb.r, pb.kappa, pb.f, pb.phi)
+            assert rel_maxnorm(outs1[i], R[-1]) <= 1e-8
+    b.close()
