@@ -721,7 +721,7 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
   double* ck = snap ? p.ckpt + size_t((m - 1) / p.ckpt_every - 1) * size_t(nexp + 2 * kRing) * p.vlen : nullptr;
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
-    double acc[2] = {0.0, 0.0};
+    double acc[3] = {0.0, 0.0, 0.0};   // (b,b), (r0,r0), kappa entries not > 0
     for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
       int i0, sl;
       item(pl, t, idx, i0, sl);
@@ -791,6 +791,7 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
           r0 = mask2(make_double2(b.x - (bm * x0.x + kk.x * ax.x), b.y - (bm * x0.y + kk.y * ax.y)), i0, p.n);
         }
         st2(p.kap, off, kk);
+        acc[2] += (kk.x > 0.0 ? 0.0 : 1.0) + (i0 + 1 < p.n && !(kk.y > 0.0) ? 1.0 : 0.0);
         if (kscale) st2(p.dsc, off, mask2(make_double2(kb / kk.x, kb / kk.y), i0, p.n));
         if (ctl.hist_lo >= 0) st2(p.uhist + size_t(m - 1 - ctl.hist_lo) * p.vlen, off, a1);
       }
@@ -809,8 +810,8 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
         lbuf<RP>(L)[sl] = tocx<RP>(pc_in(p, off, b));
       }
     }
-    const int sls[2] = {SL_BB, SL_RR};
-    write_partials<2>(p, tile, sls, acc);
+    const int sls[3] = {SL_BB, SL_RR, SL_KB};
+    write_partials<3>(p, tile, sls, acc);
     if (warm && !fused) tileA_fft_store<double>(pl, tile, L.bd, p.T);
     else tileA_fft_store<RP>(pl, tile, lbuf<RP>(L), pT<RP>(p));
   }
@@ -919,7 +920,7 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
     if (ctl.pending) tileC_load_ifft<double>(pl, tile, p.T, L.bd);
-    double acc[1] = {0.0};
+    double acc[2] = {0.0, 0.0};   // (b,b), kappa entries not > 0
     for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
       int i0, sl;
       item(pl, t, idx, i0, sl);
@@ -942,6 +943,7 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
           x0 = mask2(x0, i0, p.n);
         }
         st2(p.kap, off, kk);
+        acc[1] += (kk.x > 0.0 ? 0.0 : 1.0) + (i0 + 1 < p.n && !(kk.y > 0.0) ? 1.0 : 0.0);
         if (kscale) st2(p.dsc, off, mask2(make_double2(kb / kk.x, kb / kk.y), i0, p.n));
       }
       st2(p.vec[VB], off, b);
@@ -955,8 +957,8 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
         lbuf<RP>(L)[sl] = tocx<RP>(pc_in(p, off, b));
       }
     }
-    const int sls[1] = {SL_BB};
-    write_partials<1>(p, tile, sls, acc);
+    const int sls[2] = {SL_BB, SL_KB};
+    write_partials<2>(p, tile, sls, acc);
     if (warm) tileA_fft_store<double>(pl, tile, L.bd, p.T);
     else tileA_fft_store<RP>(pl, tile, lbuf<RP>(L), pT<RP>(p));
   }
@@ -1209,13 +1211,19 @@ __device__ __forceinline__ int level_start(const Prob& p, int m, int rank, Ctl& 
     phase_rhs<double>(p, m, rank, L, fused, ctl);
   }
   BARRIER();
-  double red2[2];
+  double red3[3];
   {
-    const int sl[2] = {SL_BB, SL_RR};
-    reduce_slots<2>(p, sl, red2);
+    const int sl[3] = {SL_BB, SL_RR, SL_KB};
+    reduce_slots<3>(p, sl, red3);
   }
-  bb = red2[0];
-  rr0 = fused ? red2[1] : bb;
+  // the method needs kappa > 0 (the problem statement of (1.1)); a level with
+  // kappa^m not > 0 somewhere (or NaN) is reported as FIDS_ENUMERIC
+  if (red3[2] != 0.0) {
+    write_info(p, rank, m, 0, 0, NAN, FIDS_ENUMERIC);
+    return FIDS_ENUMERIC;
+  }
+  bb = red3[0];
+  rr0 = fused ? red3[1] : bb;
   double red1[1];
   if (p.x0_mode != 0 && !fused) {
     phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd, L);

@@ -177,3 +177,17 @@ def test_error_paths():
     with pytest.raises(fids.FidsError) as e:
         gpu_solve(bad)
     assert e.value.status == fids.FIDS_ENUMERIC
+
+
+@pytest.mark.parametrize("value", [0.0, -0.5, np.nan])
+@pytest.mark.parametrize("kw", [VARIANTS[0], VARIANTS[3]])
+def test_nonpositive_kappa_is_reported(value, kw):
+    """kappa must be positive (problem statement of (1.1)); a level whose kappa
+    is not somewhere is FIDS_ENUMERIC, and the levels before it complete."""
+    from paper_2002_11978_amd import fids
+    pb = W.seeded(1.5, 0.5, 300, 6)
+    pb.kappa = pb.kappa.copy()
+    pb.kappa[3, 123] = value            # kappa at t_4
+    with pytest.raises(fids.FidsError) as e:
+        gpu_solve(pb, **kw)
+    assert e.value.status == fids.FIDS_ENUMERIC
