@@ -1150,9 +1150,13 @@ int fids_batch_tune(fids_batch* b, int32_t levels, int32_t* tile_ct) {
       for (int mul : {1, 2, 4}) {
         PlanShape ps = plan_shape(base.Nc, ng * mul, ng, 0, cap);
         if (ps.N1 != base.N1 || ps.N2 != base.N2) continue;
-        Prob trial = keep;
-        trial.pl.CT = ps.CT; trial.pl.ntiles = ps.ntiles; trial.pl.RU = ps.RU; trial.pl.nrg = ps.nrg;
-        const size_t lds = fids::level_lds_bytes(trial);
+        // the LDS need grows with each member's SOE node count: it must fit for all of the class
+        size_t lds = 0;
+        for (int i : kv.second) {
+          Prob t = b->members[size_t(i)]->hp;
+          t.pl.CT = ps.CT; t.pl.ntiles = ps.ntiles; t.pl.RU = ps.RU; t.pl.nrg = ps.nrg;
+          lds = std::max(lds, fids::level_lds_bytes(t));
+        }
         if (lds + 4096 > size_t(max_lds)) continue;   // room for the kernel's static LDS
         bool dup = false;
         for (const Cand& c : cands) dup |= (c.ps.CT == ps.CT && c.ps.RU == ps.RU);
@@ -1165,7 +1169,7 @@ int fids_batch_tune(fids_batch* b, int32_t levels, int32_t* tile_ct) {
       trial.g0 = 0;
       trial.slot_first = 0;
       trial.status = keep.status;
-      HIPCHK(hipMemcpyAsync(rep_h->dp, &trial, sizeof(Prob), hipMemcpyHostToDevice, b->stream));
+      HIPCHK(hipMemcpy(rep_h->dp, &trial, sizeof(Prob), hipMemcpyHostToDevice));
       HIPCHK(fids::launch_init_state(trial, rep_h->dp, b->stream));
       HIPCHK(hipMemsetAsync(trial.F, 0, size_t(trial.nexp) * trial.vlen * 8, b->stream));
       HIPCHK(hipMemsetAsync(trial.AU, 0, size_t(fids::kRing) * trial.vlen * 8, b->stream));
@@ -1193,7 +1197,7 @@ int fids_batch_tune(fids_batch* b, int32_t levels, int32_t* tile_ct) {
       fids_problem* h = b->members[size_t(i)];
       h->hp.pl.CT = cands[best].ps.CT; h->hp.pl.ntiles = cands[best].ps.ntiles;
       h->hp.pl.RU = cands[best].ps.RU; h->hp.pl.nrg = cands[best].ps.nrg;
-      h->lds = cands[best].lds;
+      h->lds = fids::level_lds_bytes(h->hp);
       if (tile_ct) tile_ct[i] = cands[best].ps.CT;
     }
   }

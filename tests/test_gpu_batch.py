@@ -197,3 +197,24 @@ def test_batch_tune_keeps_results():
             R = oracle.dids_solve(pb.alpha, pb.gamma, pb.n, pb.M, pb.r, pb.kappa, pb.f, pb.phi)
             assert rel_maxnorm(outs1[i], R[-1]) <= 1e-8
     b.close()
+
+
+def test_batch_tune_class_with_uneven_soe_sizes():
+    """Members of one class (equal embedding length and group) have different
+    SOE node counts, so different LDS needs; the tuned tiling must fit the
+    largest of them (a too-small LDS allocation corrupts results silently).
+    Tuned results stay within rounding of the untuned batch."""
+    M = 24
+    pbs = [pb for pb in (W.batch_member(p, M=M) for p in range(256)) if 4096 < pb.n <= 8192][:24]
+    assert len(pbs) >= 8
+    b = _batch(pbs, solver=1, precision=0, x0_mode=3, precond=2, krylov_tol=1e-10)
+    ref = [o.cpu().numpy() for o in b.solve_all()[0]]
+    b.reset()
+    ct = b.tune(levels=2)
+    say(f"  tuned columns per tile {sorted(set(ct))}")
+    outs, reps = b.solve_all()
+    st, last = b.status()
+    assert st == [0] * len(pbs)
+    for a, o in zip(ref, outs):
+        assert rel_maxnorm(o.cpu().numpy(), a) <= 1e-9
+    b.close()
