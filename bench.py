@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--forms", default="headline,plain,mixed")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-levels", type=int, default=24)
+    ap.add_argument("--cpu-levels", type=int, default=100)
     ap.add_argument("--cpu-n", type=int, default=4095)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
