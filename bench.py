@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--table11", action="store_true",
+                    help="Table 11 rows (Example 2) on the GPU: fast/direct history, with/without preconditioner")
     ap.add_argument("--profile-pass", action="store_true",
                     help="one headline launch of the level kernel plus a 256 MiB device copy (for counters)")
     return ap.parse_args()
@@ -215,6 +217,61 @@ def batch_leg(tol, count):
               f"its {its.mean():.2f}, fp64-pc levels {(fb > 0).sum()}", file=sys.stderr, flush=True)
         b.close()
     return out
+
+
+# Table 11 rows (r, gamma, alpha, N_p, M) with the paper's printed Err_inf and
+# FIDS+P iterations per level and CPU seconds (i5-8265U, MATLAB; context only)
+TABLE11 = [
+    (2, 0.5, 1.5, 64, 431, 6.362e-4, 7.7, 0.347), (2, 0.5, 1.5, 128, 1449, 1.542e-4, 7.9, 1.689),
+    (2, 0.5, 1.5, 256, 4871, 4.469e-5, 8.0, 6.698), (2, 0.5, 1.5, 512, 16384, 1.333e-5, 8.2, 43.338),
+    (3, 0.8, 1.5, 128, 431, 1.381e-4, 6.6, 0.439), (3, 0.8, 1.5, 256, 1184, 3.265e-5, 6.9, 1.545),
+    (3, 0.8, 1.5, 512, 3251, 7.897e-6, 7.1, 8.143), (3, 0.8, 1.5, 1024, 8934, 2.319e-6, 7.0, 34.543),
+    (2, 0.5, 1.9, 64, 862, 1.446e-3, 7.9, 0.748), (2, 0.5, 1.9, 128, 3327, 3.533e-4, 7.9, 3.838),
+    (2, 0.5, 1.9, 256, 12855, 8.636e-5, 8.1, 18.073), (2, 0.5, 1.9, 512, 49668, 2.112e-5, 8.1, 132.04),
+    (3, 0.8, 1.9, 128, 862, 3.521e-4, 7.3, 1.049), (3, 0.8, 1.9, 256, 2656, 8.596e-5, 7.3, 3.679),
+    (3, 0.8, 1.9, 512, 8192, 2.100e-5, 7.4, 21.436), (3, 0.8, 1.9, 1024, 25268, 5.136e-6, 7.3, 86.540),
+]
+
+
+def table11_leg():
+    """Example 2 at the Table 11 sizes with the paper's solver settings
+    (BiCGSTAB, tol 1e-10, zero initial guess, SOE 1e-9): fast history with the
+    Strang preconditioner (FIDS+P), without it (FIDS+I), and the direct
+    history with it (DIDS+P); Err_inf against the exact solution."""
+    import torch
+
+    from paper_2002_11978_amd import fids
+    from paper_2002_11978_amd import workloads as W
+    dev = torch.device("cuda:0")
+    rows = []
+    for (r, g, a, Np, M, err_p, its_p, cpu_s) in TABLE11:
+        pb = W.example2(a, g, r, Np, M)
+        k, f, phi = (torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (pb.kappa, pb.f, pb.phi))
+        row = {"r": r, "gamma": g, "alpha": a, "N": Np, "M": M, "paper_err_inf": err_p, "paper_its": its_p,
+               "paper_cpu_s": cpu_s}
+        for name, extra in (("fids_p", dict(precond=0, history=0)), ("fids_i", dict(precond=1, history=0)),
+                            ("dids_p", dict(precond=0, history=1))):
+            if name == "fids_i" and M > 10000:
+                continue
+            if name == "dids_p" and M > 30000:
+                continue
+            prm = fids.default_params(alpha=a, gamma=g, n=pb.n, M=M, r=r, soe_tol=1e-9, krylov_tol=1e-10,
+                                      krylov_maxit=2000, solver=0, precision=0, x0_mode=0,
+                                      store_states=int(name != "dids_p"), **extra)
+            prob = fids.Problem(prm, k, f, phi)
+            prob.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            uT, U, reps = prob.solve_all(return_all=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ei = float(np.max(np.abs(U.cpu().numpy() - pb.exact)))      # Err_inf = max_m ||u^m - u(t_m)||_inf
+            row[name] = {"s": dt, "levels_per_s": M / dt, "its": float(np.mean([x.matvecs for x in reps]) / 2),
+                         "err_inf": ei}
+            prob.close()
+        print(f"[bench] table11 {row}", file=sys.stderr, flush=True)
+        rows.append(row)
+    return rows
 
 
 class Runner:
@@ -409,6 +466,8 @@ def main():
         out["adj_fwd_ratio"] = out["adjoint"]["adj_over_fwd"]
     if not args.no_batch:
         out["batch"] = batch_leg(args.tol, args.batch_count)
+    if args.table11:
+        out["table11"] = table11_leg()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out))

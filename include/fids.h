@@ -69,6 +69,8 @@ extern "C" {
                           /* with the FP64 preconditioner                          */
 #define FIDS_STRANG   0   /* Strang circulant preconditioner, eq. (4.3)              */
 #define FIDS_NONE     1   /* no preconditioner (identity)                            */
+#define FIDS_HISTORY_SOE    0  /* fast history: SOE recurrence (FIDS)              */
+#define FIDS_HISTORY_DIRECT 1  /* direct history: full L1 sum (DIDS, eq. 4.1)      */
 #define FIDS_STRANG_K 2   /* kappa-scaled Strang: P = K_m C_m, C_m the Strang        */
                           /* circulant of b_m'/kbar_m I + A (same symbols as       */
                           /* FIDS_STRANG, input scaled by kbar_m / kappa_i^m)      */
@@ -109,6 +111,11 @@ typedef struct fids_params {
     int32_t soe_helpers;  /* workgroups that stream the SOE history one level      */
                           /* ahead of the solve: -1 auto, 0 none, k > 0 exactly k  */
                           /* (ignored, i.e. 0, when checkpoint_every > 0)          */
+    int32_t history;      /* FIDS_HISTORY_SOE: the fast scheme (sum-of-exponentials */
+                          /* history recurrence, Lemma 2.2); FIDS_HISTORY_DIRECT: */
+                          /* the direct scheme (4.1), the full graded-L1 sum over */
+                          /* every earlier state (keeps all states; O(m n) per    */
+                          /* level; no adjoint, no batch)                         */
     int32_t checkpoint_every; /* C > 0: the forward run snapshots its state (u^{m-1},*/
                           /* u^{m-2}, the SOE history F^{(m-1)}) at levels         */
                           /* m = kC + 1 and fids_adjoint recomputes each segment   */
@@ -134,7 +141,7 @@ typedef struct fids_problem fids_problem;
 /* Fills *p with: alpha 1.5, gamma 0.5, l 1, T 1, n 255, M 64, r 3, mu 0,
  * soe_tol 1e-10, krylov_tol 1e-12, krylov_maxit 200, restart 20, BiCGSTAB,
  * FP64, Strang, kappa_time_dependent 1, x0_mode 0, store_states 0, wg_count 0,
- * soe_helpers -1, checkpoint_every 0. */
+ * soe_helpers -1, history FIDS_HISTORY_SOE, checkpoint_every 0. */
 int fids_params_default(fids_params* p);
 
 /* Bytes of device workspace the problem needs (256-byte multiple).
@@ -277,6 +284,11 @@ int fids_ifl_column(int64_t n, double alpha, double l, double mu, double* col);
 
 /* Eigenvalues of Strang's circulant s(A), lam[k] = sum_j c_S[j] cos(2 pi jk/n). */
 int fids_strang_eigs(int64_t n, double alpha, double l, double mu, double* lam);
+
+/* Row m of the direct scheme's history weights (eq. 4.1, 1 <= m <= M <= 65536):
+ * w[k], k = 0..m-1, such that b^m = sum_k w[k] u^k + f^m, i.e. w[0] = g a_1^{(m)},
+ * w[k] = g (a_{k+1}^{(m)} - a_k^{(m)}) with g = 1 / Gamma(1 - gamma). */
+int fids_direct_weights(double gamma, double T, int64_t M, double r, int64_t m, double* w);
 
 /* b_m = tau_m^{-gamma} / Gamma(2-gamma) for m = 1..M into beta[m-1]. */
 int fids_level_coefficients(double gamma, double T, int64_t M, double r, double* beta);

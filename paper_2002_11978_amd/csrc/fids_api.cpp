@@ -88,6 +88,7 @@ struct Layout {
   size_t Tb, q, Tq;
   size_t u[fids::kRing], F, kap, dsc, vec[10], uhist, T, Tf, tau, V, Z, Zf, soec, H1, AU, sync2, hflag;
   // adjoint: segment snapshots and the adjoint descriptor's state
+  size_t dhw;
   size_t ckpt, aprob, ainfo, astatus, ubar[3], yr[fids::kRing], Fbar, alam, gk, AUa;
   int nck;          // snapshots held (levels kC + 1, k = 1..nck)
   int hist_cap;     // states uhist holds
@@ -165,11 +166,14 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   lo.AU = take(size_t(fids::kRing) * L * 8);
   for (int i = 0; i < 10; ++i) lo.vec[i] = take(L * 8);
   const size_t C = size_t(std::max(p.checkpoint_every, 0));
-  lo.hist_cap = p.store_states ? int(M + 1) : (C > 0 ? int(std::min(C, M) + 1) : 0);
+  const bool direct = p.history == FIDS_HISTORY_DIRECT;
+  lo.dhw = direct ? take(M * (M + 1) / 2 * 8) : 0;
+  // the direct history reads every earlier state
+  lo.hist_cap = (p.store_states || direct) ? int(M + 1) : (C > 0 ? int(std::min(C, M) + 1) : 0);
   lo.uhist = lo.hist_cap ? take(size_t(lo.hist_cap) * L * 8) : 0;
-  lo.nck = (!p.store_states && C > 0) ? int((M - 1) / C) : 0;
+  lo.nck = (!p.store_states && !direct && C > 0) ? int((M - 1) / C) : 0;
   lo.ckpt = lo.nck ? take(size_t(lo.nck) * (ne + 2 * fids::kRing) * L * 8) : 0;
-  if (p.store_states || C > 0) {
+  if (!direct && (p.store_states || C > 0)) {
     lo.aprob = take(sizeof(Prob));
     lo.ainfo = take(M * sizeof(fids_step_info));
     lo.astatus = take(4 * sizeof(int));
@@ -266,6 +270,7 @@ struct fids_problem {
   // host copies kept alive for asynchronous uploads
   std::vector<std::vector<double2>> keep2;
   std::vector<std::vector<float2>> keepf;
+  std::vector<double> keepd;     // direct-history weights
 };
 
 struct fids_batch {
@@ -428,6 +433,11 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   fids_params pb = *pin;
   if (batch) batch_params(pb, batch_group);
   const fids_params* p = &pb;
+  if (pb.history == FIDS_HISTORY_DIRECT) {
+    pb.store_states = 1;      // every earlier state is read by the direct history
+    pb.checkpoint_every = 0;
+    pb.soe_helpers = 0;
+  }
   fids_problem* h = new (std::nothrow) fids_problem();
   if (!h) return FIDS_EINVAL;
   h->prm = *p;
@@ -463,6 +473,10 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
     st |= upload(h, o, h->keep2.back().data(), h->keep2.back().size() * 16);
     st |= upload(h, of, h->keepf.back().data(), h->keepf.back().size() * 8);
   };
+  if (lo.dhw) {
+    h->keepd = fids::direct_history_weights(p->T, p->M, p->r, p->gamma);
+    st |= upload(h, lo.dhw, h->keepd.data(), h->keepd.size() * 8);
+  }
   put2(lo.tw1r, lo.tw1rf, twiddles(h->sh.pr.N1));
   put2(lo.tw2r, lo.tw2rf, twiddles(h->sh.pr.N2));
   put2(lo.tw1c, lo.tw1cf, twiddles(h->sh.pc.N1));
@@ -500,6 +514,8 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   hp.zf = lo.Zf ? at<float>(ws, lo.Zf) : nullptr;
   hp.uhist = lo.uhist ? at<double>(ws, lo.uhist) : nullptr;
   hp.T = at<double2>(ws, lo.T); hp.Tf = at<float2>(ws, lo.Tf);
+  hp.history = p->history;
+  hp.dhw = lo.dhw ? at<double>(ws, lo.dhw) : nullptr;
   hp.ckpt_every = std::max(p->checkpoint_every, 0);
   hp.ckpt = lo.ckpt ? at<double>(ws, lo.ckpt) : nullptr;
   hp.adjoint = 0;
@@ -699,6 +715,7 @@ int batch_layout(const fids_params* p, int32_t count, BatchLayout& bl) {
   for (int32_t i = 0; i < count; ++i) {
     // one kernel instance serves the batch: members share M and the solver variant
     if (p[i].M != M || p[i].solver != p[0].solver || p[i].precision != p[0].precision) return FIDS_EINVAL;
+    if (p[i].history != FIDS_HISTORY_SOE) return FIDS_EINVAL;
     fids_params q = p[i];
     batch_params(q);
     Shapes sh;
@@ -1273,6 +1290,15 @@ int fids_strang_eigs(int64_t n, double alpha, double l, double mu, double* lam) 
   if (!(me > alpha && me <= 2)) return FIDS_EINVAL;
   const auto e = fids::strang_eigs(fids::ifl_column(n, alpha, l, me));
   std::copy(e.begin(), e.end(), lam);
+  return FIDS_OK;
+}
+
+int fids_direct_weights(double gamma, double T, int64_t M, double r, int64_t m, double* w) {
+  if (!w || M < 1 || m < 1 || m > M || M > (int64_t(1) << 16) || !(gamma > 0 && gamma < 1) || !(T > 0) || !(r >= 1))
+    return FIDS_EINVAL;
+  const std::vector<double> all = fids::direct_history_weights(T, M, r, gamma);
+  const double* row = all.data() + size_t(m - 1) * size_t(m) / 2;
+  std::copy(row, row + m, w);
   return FIDS_OK;
 }
 

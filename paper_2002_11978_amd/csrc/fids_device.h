@@ -88,6 +88,9 @@ struct Prob {
   double* AU;                   // [kRing][vlen] A u^k of the last levels, slot k % kRing
   unsigned* sync2;              // [0]: helper step completions, [64]: last completed level
   unsigned* hflag;              // [nh][64]: per-helper release flags (one 256-byte line each)
+  // direct history (the scheme (4.1)): b^m = sum_{k<m} dhw[(m-1) m / 2 + k] u^k + f^m
+  int history;                  // FIDS_HISTORY_SOE | FIDS_HISTORY_DIRECT
+  const double* dhw;            // [M (M + 1) / 2] weights (g included), or null
   // forward snapshots for the adjoint's segment recomputation
   int ckpt_every;               // C (0: none)
   double* ckpt;                 // [(M-1)/C][nexp + 2 kRing][vlen]: u^{m-1..m-kRing}, A u^{m-1..m-kRing},

@@ -676,6 +676,8 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
   const Plan& pl = L.pl;
   const int nexp = p.nexp;
   const bool self_soe = p.nh == 0;
+  const bool direct = p.history == FIDS_HISTORY_DIRECT;
+  const double* dw = direct ? p.dhw + size_t(m - 1) * size_t(m) / 2 : nullptr;
   double* th = L.tab;
   double* de = L.tab + nexp;
   double* gw = L.tab + 2 * nexp;
@@ -731,7 +733,19 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
         const double2 a1 = ld2(um1, off);
         double2 h = make_double2(0.0, 0.0);
         double2 d = make_double2(0.0, 0.0);
-        if (m >= 2) {
+        double2 dsum = make_double2(0.0, 0.0);   // direct scheme: sum_{k<m} w_k u^k
+        if (direct) {
+          dsum = make_double2(dw[m - 1] * a1.x, dw[m - 1] * a1.y);
+          for (int k = 0; k < m - 1; ++k) {
+            const double2 uk = ld2(p.uhist + size_t(k) * p.vlen, off);
+            dsum.x += dw[k] * uk.x;
+            dsum.y += dw[k] * uk.y;
+          }
+          if (m >= 2) {
+            const double2 a2 = ld2(um2, off);
+            d = make_double2(a1.x - a2.x, a1.y - a2.y);
+          }
+        } else if (m >= 2) {
           const double2 a2 = ld2(um2, off);
           if (snap)
             for (int k = 0; k < kRing; ++k) {
@@ -762,7 +776,8 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
         }
         const double2 fv = nat2(fm, i0, p.n);
         const double2 kk = nat2(km, i0, p.n);
-        b = mask2(make_double2(bm * a1.x - h.x + fv.x, bm * a1.y - h.y + fv.y), i0, p.n);
+        b = direct ? mask2(make_double2(dsum.x + fv.x, dsum.y + fv.y), i0, p.n)
+                   : mask2(make_double2(bm * a1.x - h.x + fv.x, bm * a1.y - h.y + fv.y), i0, p.n);
         if (npts == 2) {
           x0 = mask2(make_double2(a1.x + rho * d.x, a1.y + rho * d.y), i0, p.n);
         } else if (npts > 0) {

@@ -31,6 +31,9 @@ int validate(const fids_params& p) {
   if (p.wg_count < 0 || p.wg_count > 4096) return FIDS_EINVAL;
   if (p.soe_helpers < -1 || p.soe_helpers > 4096) return FIDS_EINVAL;
   if (p.checkpoint_every < 0) return FIDS_EINVAL;
+  if (p.history != FIDS_HISTORY_SOE && p.history != FIDS_HISTORY_DIRECT) return FIDS_EINVAL;
+  // the direct history keeps a triangular table of M (M + 1) / 2 weights
+  if (p.history == FIDS_HISTORY_DIRECT && p.M > (int64_t(1) << 16)) return FIDS_EINVAL;
   if (p.n > (int64_t(1) << 21) || p.M > (int64_t(1) << 24)) return FIDS_EINVAL;
   return FIDS_OK;
 }
@@ -51,6 +54,45 @@ std::vector<double> step_sizes(double T, int64_t M, double r) {
     tau[m] = (m == 1) ? tm : -tm * std::expm1(r * std::log1p(-1.0 / double(m)));
   }
   return tau;
+}
+
+// ---------------------------------------------------------------- direct history
+// Graded-L1 weights a_k^{(m)} = (1/tau_k) int_{t_{k-1}}^{t_k} (t_m - s)^{-gamma} ds
+// = [D_{k-1}^{1-gamma} - D_k^{1-gamma}] / ((1 - gamma) tau_k), D_j = t_m - t_j, k = 1..m
+// (Sec. 2.1).  D_j = t_m (1 - (j/m)^r) is formed with expm1/log1p, the
+// difference of powers as -D_{k-1}^nu expm1(nu log1p(-tau_k / D_{k-1})), and the
+// last interval exactly (D_m = 0: a_m = tau_m^{-gamma} / (1 - gamma)); there
+// tau_m / D_{m-1} = 1 up to rounding, and the residue's small power (nu = 1 -
+// gamma) would not be small.
+static std::vector<double> l1_row(double T, int64_t M, double r, double gamma, int64_t m,
+                                  const std::vector<double>& tau) {
+  std::vector<double> a(size_t(m) + 1, 0.0);
+  const double tm = T * std::pow(double(m) / double(M), r);
+  const double nu = 1.0 - gamma;
+  auto dist = [&](int64_t j) {           // t_m - t_j, 0 <= j < m
+    return j == 0 ? tm : -tm * std::expm1(r * std::log1p(double(j - m) / double(m)));
+  };
+  for (int64_t k = 1; k < m; ++k) {
+    // D_k / D_{k-1} = 1 - tau_k / D_{k-1}: the step itself, not a difference of distances
+    const double d0 = dist(k - 1);
+    a[size_t(k)] = -std::pow(d0, nu) * std::expm1(nu * std::log1p(-tau[k] / d0)) / (nu * tau[k]);
+  }
+  a[size_t(m)] = std::pow(tau[m], -gamma) / nu;
+  return a;
+}
+
+std::vector<double> direct_history_weights(double T, int64_t M, double r, double gamma) {
+  const std::vector<double> tau = step_sizes(T, M, r);
+  const double g = 1.0 / std::tgamma(1.0 - gamma);
+  std::vector<double> w(size_t(M) * size_t(M + 1) / 2, 0.0);
+  for (int64_t m = 1; m <= M; ++m) {
+    const std::vector<double> a = l1_row(T, M, r, gamma, m, tau);
+    double* row = w.data() + size_t(m - 1) * size_t(m) / 2;
+    // b^m = g [a_1 u^0 + sum_{k=1}^{m-1} (a_{k+1} - a_k) u^k] + f^m  (eq. 4.1)
+    row[0] = g * a[1];
+    for (int64_t k = 1; k <= m - 1; ++k) row[k] = g * (a[size_t(k + 1)] - a[size_t(k)]);
+  }
+  return w;
 }
 
 // ---------------------------------------------------------------- IFL column

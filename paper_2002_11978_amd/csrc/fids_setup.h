@@ -57,6 +57,10 @@ int soe_build(double gamma, double delta, double T, double tol, SoeNodes& out);
 double soe_max_rel_error(const SoeNodes& q, double gamma, double delta, double T, int npts);
 std::vector<double> step_sizes(double T, int64_t M, double r);
 
+// Direct-history weights of eq. (4.1): row m (offset (m-1) m / 2) holds the
+// coefficients of u^0..u^{m-1} in b^m (g included).
+std::vector<double> direct_history_weights(double T, int64_t M, double r, double gamma);
+
 // Full set-up; returns FIDS_OK / FIDS_EINVAL.
 int build_tables(const fids_params& p, HostTables& t);
 

@@ -21,6 +21,7 @@ FIDS_OK, FIDS_EINVAL, FIDS_EDEVICE, FIDS_ENOCONV, FIDS_ENUMERIC, FIDS_ESTATE = 0
 FIDS_BICGSTAB, FIDS_FGMRES = 0, 1
 FIDS_FP64, FIDS_MIXED = 0, 1
 FIDS_STRANG, FIDS_NONE, FIDS_STRANG_K = 0, 1, 2
+FIDS_HISTORY_SOE, FIDS_HISTORY_DIRECT = 0, 1
 
 
 class Params(ctypes.Structure):
@@ -32,7 +33,7 @@ class Params(ctypes.Structure):
         ("restart", ctypes.c_int32), ("solver", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("precond", ctypes.c_int32), ("kappa_time_dependent", ctypes.c_int32),
         ("x0_mode", ctypes.c_int32), ("store_states", ctypes.c_int32), ("wg_count", ctypes.c_int32),
-        ("soe_helpers", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
+        ("soe_helpers", ctypes.c_int32), ("history", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
     ]
 
 
@@ -92,6 +93,8 @@ _SIGS = {
     "fids_strang_eigs": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]),
     "fids_level_coefficients": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                                ctypes.c_double, _D]),
+    "fids_direct_weights": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_double,
+                                           ctypes.c_int64, _D]),
 }
 
 
@@ -190,6 +193,13 @@ def batch_plan(params, resident):
     mk = ctypes.c_double(0.0)
     _check(lib().fids_batch_plan(arr, count, resident, ng, slot, ctypes.byref(mk)), "fids_batch_plan")
     return list(ng), list(slot), mk.value
+
+
+def direct_weights(gamma, T, M, r, m):
+    import numpy as np
+    out = np.zeros(m)
+    _check(lib().fids_direct_weights(gamma, T, M, r, m, _dptr(out)), "fids_direct_weights")
+    return out
 
 
 def level_coefficients(gamma, T, M, r):

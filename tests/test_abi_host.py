@@ -161,3 +161,28 @@ def test_batch_plan_single_workgroup_packs_everything():
     ng, slot, mk = fids.batch_plan(ps, 1)
     assert ng == [1] * 12 and len(set(slot)) == 1
     assert mk == pytest.approx(sum(_embed(p.n) for p in ps))
+
+
+@pytest.mark.parametrize("M,r,gamma,m", [(25268, 3.0, 0.8, 25268), (25268, 3.0, 0.8, 9000),
+                                         (12855, 2.0, 0.5, 12855), (64, 1.0, 0.3, 40)])
+def test_direct_weights_against_extended_precision(M, r, gamma, m):
+    """Direct-scheme weights (eq. 4.1) against the L1 integrals evaluated in
+    40-digit arithmetic, on the strongest gradings of the paper's Table 11,
+    where a naive t_m - t_k - tau_k residue would spoil the last interval."""
+    import mpmath
+    mpmath.mp.dps = 40
+    w = fids.direct_weights(gamma, 1.0, M, r, m)
+    t = lambda j: (mpmath.mpf(j) / M) ** r
+    nu = 1 - mpmath.mpf(gamma)
+    g = 1 / mpmath.gamma(1 - mpmath.mpf(gamma))
+    a = lambda k: ((t(m) - t(k - 1)) ** nu - (t(m) - t(k)) ** nu) / (nu * (t(k) - t(k - 1)))
+    # w_k = g (a_{k+1} - a_k) of two nearly equal integrals is exact to the
+    # rounding of a_k itself (about 1e-16 of g a_k, far below the sum of the row)
+    scale = float(g * a(m))
+    for k in sorted({0, 1, 2, m // 2, m - 2, m - 1}):
+        if k < 0 or k >= m:
+            continue
+        exact = g * a(1) if k == 0 else g * (a(k + 1) - a(k))
+        ak = float(g * a(max(k, 1)))
+        assert abs(w[k] - float(exact)) <= 1e-9 * abs(float(exact)) + 1e-14 * ak, (k, w[k], float(exact))
+    assert abs(float(np.sum(w)) - float(g * a(m))) <= 1e-12 * scale + 1e-12

@@ -191,3 +191,19 @@ def test_nonpositive_kappa_is_reported(value, kw):
     with pytest.raises(fids.FidsError) as e:
         gpu_solve(pb, **kw)
     assert e.value.status == fids.FIDS_ENUMERIC
+
+
+@pytest.mark.parametrize("kw", [VARIANTS[0], VARIANTS[3], VARIANTS[4]])
+@pytest.mark.parametrize("n,M", [(1, 3), (100, 12), (257, 9), (1000, 16)])
+def test_direct_history_matches_oracle(n, M, kw):
+    """history = direct: the GPU runs the direct scheme (4.1) itself, the
+    oracle's own scheme, so the two differ by the Krylov tolerance only; the
+    fast scheme stays within the SOE tolerance of both."""
+    pb = W.seeded(1.5, 0.4, n, M, kappa_seed=61, f_seed=62)
+    R = _oracle(pb)
+    Ud, _ = gpu_solve(pb, soe_tol=1e-10, krylov_tol=1e-12, history=1, **kw)
+    Uf, _ = gpu_solve(pb, soe_tol=1e-10, krylov_tol=1e-12, history=0, **kw)
+    ed, ef = rel_maxnorm(Ud, R), rel_maxnorm(Uf, R)
+    say(f"  direct vs oracle {ed:.3e}, fast vs oracle {ef:.3e}")
+    assert ed <= (1e-7 if kw.get("precision", 0) == 1 else 1e-9)
+    assert ef <= _gate(kw)
