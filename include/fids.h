@@ -108,9 +108,13 @@ typedef struct fids_params {
                           /* then needs no recomputation); 0: keep only what       */
                           /* stepping needs                                        */
     int32_t wg_count;     /* workgroups that cooperate on one problem; 0 = auto    */
-    int32_t soe_helpers;  /* workgroups that stream the SOE history one level      */
-                          /* ahead of the solve: -1 auto, 0 none, k > 0 exactly k  */
-                          /* (ignored, i.e. 0, when checkpoint_every > 0)          */
+    int32_t soe_helpers;  /* workgroups that stream the history one level ahead   */
+                          /* of the solve (the SOE recurrence, or the direct sum   */
+                          /* over the stored states): -1 auto (SOE: none; direct:  */
+                          /* every workgroup the solver group leaves free), 0      */
+                          /* none, k > 0 at most k (as many as can be resident     */
+                          /* beside the group, at most 1024); 0 when               */
+                          /* checkpoint_every > 0                                  */
     int32_t history;      /* FIDS_HISTORY_SOE: the fast scheme (sum-of-exponentials */
                           /* history recurrence, Lemma 2.2); FIDS_HISTORY_DIRECT: */
                           /* the direct scheme (4.1), the full graded-L1 sum over */

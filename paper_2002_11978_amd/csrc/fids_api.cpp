@@ -88,7 +88,8 @@ struct Layout {
   size_t Tb, q, Tq;
   size_t u[fids::kRing], F, kap, dsc, vec[10], uhist, T, Tf, tau, V, Z, Zf, soec, H1, AU, sync2, hflag;
   // adjoint: segment snapshots and the adjoint descriptor's state
-  size_t dhw;
+  size_t dhw, dpart;
+  int djc_cap;      // direct history: state chunks dpart holds per slot
   size_t ckpt, aprob, ainfo, astatus, ubar[3], yr[fids::kRing], Fbar, alam, gk, AUa;
   int nck;          // snapshots held (levels kC + 1, k = 1..nck)
   int hist_cap;     // states uhist holds
@@ -168,6 +169,8 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   const size_t C = size_t(std::max(p.checkpoint_every, 0));
   const bool direct = p.history == FIDS_HISTORY_DIRECT;
   lo.dhw = direct ? take(M * (M + 1) / 2 * 8) : 0;
+  lo.djc_cap = direct ? fids::direct_chunks(n, fids::kMaxHelpers) : 0;
+  lo.dpart = direct ? take(size_t(2) * size_t(lo.djc_cap) * L * 8) : 0;
   // the direct history reads every earlier state
   lo.hist_cap = (p.store_states || direct) ? int(M + 1) : (C > 0 ? int(std::min(C, M) + 1) : 0);
   lo.uhist = lo.hist_cap ? take(size_t(lo.hist_cap) * L * 8) : 0;
@@ -436,7 +439,6 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   if (pb.history == FIDS_HISTORY_DIRECT) {
     pb.store_states = 1;      // every earlier state is read by the direct history
     pb.checkpoint_every = 0;
-    pb.soe_helpers = 0;
   }
   fids_problem* h = new (std::nothrow) fids_problem();
   if (!h) return FIDS_EINVAL;
@@ -516,6 +518,8 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   hp.T = at<double2>(ws, lo.T); hp.Tf = at<float2>(ws, lo.Tf);
   hp.history = p->history;
   hp.dhw = lo.dhw ? at<double>(ws, lo.dhw) : nullptr;
+  hp.dpart = lo.dpart ? at<double>(ws, lo.dpart) : nullptr;
+  hp.dec = hp.djc = hp.dact = 0;
   hp.ckpt_every = std::max(p->checkpoint_every, 0);
   hp.ckpt = lo.ckpt ? at<double>(ws, lo.ckpt) : nullptr;
   hp.adjoint = 0;
@@ -558,11 +562,21 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
     }
     // auto = none: on MI355X at n = 65535 the helpers' stream slowed the
     // latency-bound solve more than it saved (976 -> 897 levels/s with 128)
-    int nh = p->soe_helpers >= 0 ? p->soe_helpers : env_int("FIDS_HELPERS", 0);
-    nh = std::max(0, std::min({nh, resident - hp.ng, 1024}));   // hflag holds 1024 lines
+    // The direct history's sum over every earlier state, on the other hand,
+    // is a stream of m n values per level: auto = every free workgroup.
+    const bool direct = p->history == FIDS_HISTORY_DIRECT;
+    int nh = p->soe_helpers >= 0 ? p->soe_helpers : (direct ? fids::kMaxHelpers : env_int("FIDS_HELPERS", 0));
+    nh = std::max(0, std::min({nh, resident - hp.ng, fids::kMaxHelpers}));
     // snapshots are taken where the solver group streams the history itself
     if (p->checkpoint_every > 0) nh = 0;
     hp.nh = nh;
+    if (direct && nh > 0) {
+      // active rows of a tile hold the natural value pairs below ceil(n / 2)
+      hp.dact = int(((p->n + 1) / 2 + hp.pl.N2 - 1) / hp.pl.N2);
+      const int nact = hp.pl.ntiles * hp.dact * hp.pl.CT;
+      hp.dec = (nact + fids::kThreads - 1) / fids::kThreads;
+      hp.djc = std::max(1, std::min(nh / hp.dec, lo.djc_cap));
+    }
   }
   if (lo.aprob) {
     Prob& ha = h->ha;
@@ -862,10 +876,7 @@ int fids_solve_all(fids_problem* h, double* uT_d, double* u_all_d, fids_step_inf
   const int st = run_levels(h, h->sh.M, per_step);
   if (st != FIDS_OK) return st;
   if (uT_d) HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.u[h->sh.M % fids::kRing], uT_d, h->stream));
-  if (u_all_d)
-    for (int64_t m = 0; m <= h->sh.M; ++m)
-      HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.uhist + size_t(m) * h->hp.vlen,
-                                     u_all_d + size_t(m) * h->sh.n, h->stream));
+  if (u_all_d) HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.uhist, u_all_d, h->stream, h->sh.M + 1));
   HIPCHK(hipStreamSynchronize(h->stream));
   return FIDS_OK;
 }

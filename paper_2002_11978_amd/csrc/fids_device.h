@@ -18,6 +18,16 @@ constexpr int kThreads = 512;     // threads per workgroup in every kernel
 constexpr int kMaxFFT = 4096;     // longest per-workgroup FFT (complex points)
 constexpr int kMaxRestart = 32;
 constexpr int kRing = 4;          // states kept: u^m lives in u[m % kRing] (and A u^m in AU)
+constexpr int kMaxHelpers = 1024; // helper workgroups (one release-flag line each)
+constexpr int kDirectChunks = 128; // direct history: most state chunks per element block
+
+// Direct history with helpers: state chunks for nh helpers over problems of n
+// unknowns (element blocks of kThreads value pairs).
+inline int direct_chunks(int64_t n, int nh) {
+  const int64_t blocks = ((n + 1) / 2 + kThreads - 1) / kThreads;
+  const int64_t c = nh / blocks;
+  return int(c < 1 ? 1 : (c > kDirectChunks ? kDirectChunks : c));
+}
 
 // Partial-sum slots (one value per column tile each).
 enum Slot {
@@ -91,6 +101,11 @@ struct Prob {
   // direct history (the scheme (4.1)): b^m = sum_{k<m} dhw[(m-1) m / 2 + k] u^k + f^m
   int history;                  // FIDS_HISTORY_SOE | FIDS_HISTORY_DIRECT
   const double* dhw;            // [M (M + 1) / 2] weights (g included), or null
+  // with helpers (nh > 0) helper step k forms level k+1's sum without u^k in
+  // djc chunks of the states (partials dpart[(k+1) & 1][chunk][vlen]) over dec
+  // element blocks of kThreads active items (dact active rows of each tile)
+  double* dpart;
+  int dec, djc, dact;
   // forward snapshots for the adjoint's segment recomputation
   int ckpt_every;               // C (0: none)
   double* ckpt;                 // [(M-1)/C][nexp + 2 kRing][vlen]: u^{m-1..m-kRing}, A u^{m-1..m-kRing},

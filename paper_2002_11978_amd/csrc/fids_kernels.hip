@@ -15,6 +15,7 @@
 // workgroups of a problem meet at a group barrier between passes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "fids_device.h"
@@ -574,6 +575,50 @@ __device__ __forceinline__ bool wait_ge(const Prob& p, const unsigned* addr, uns
   return s_ok != 0;
 }
 
+// Direct history, helper step k (concurrent with the solve of level k): the
+// part of level k+1's sum that does not involve u^k,
+//   S^{k+1} = sum_{j<k} w_{k+1,j} u^j,
+// over chunks of j (partial c covers j in [k c / djc, k (c+1) / djc)) and
+// element blocks of kThreads active items.  u^j for j <= k-2 was stored when
+// level j+1 ran; u^{k-1} is still in the ring (its stored copy is written by
+// level k concurrently).  The solver group adds the chunks and w_{k+1,k} u^k.
+__device__ __forceinline__ void direct_helper_step(const Prob& p, int hr, int k) {
+  const Plan& pl = p.pl;
+  const int per_tile = p.dact * pl.CT;
+  const int nact = pl.ntiles * per_tile;
+  const int blk = 2 * pl.CT * pl.N1;
+  const int logCT = ilog2(pl.CT);
+  const double* wrow = p.dhw + size_t(k) * size_t(k + 1) / 2;
+  double* P = p.dpart + size_t((k + 1) & 1) * size_t(p.djc) * p.vlen;
+  const double* ulast = p.u[(k - 1) % kRing];
+  const int units = p.dec * p.djc;
+  for (int un = hr; un < units; un += p.nh) {
+    const int eb = un % p.dec, c = un / p.dec;
+    const int j0 = int(int64_t(k) * c / p.djc), j1 = int(int64_t(k) * (c + 1) / p.djc);
+    const int a = eb * kThreads + threadIdx.x;
+    if (a >= nact) continue;
+    const int tile = a / per_tile, idx = a - tile * per_tile;
+    const int i0 = 2 * (pl.N2 * (idx >> logCT) + tile * pl.CT + (idx & (pl.CT - 1)));
+    if (i0 >= p.n) continue;
+    const int off = tile * blk + 2 * idx;
+    const int js = min(j1, k - 1);
+    double2 s = make_double2(0.0, 0.0);
+    const double* up = p.uhist + size_t(j0) * p.vlen + off;
+#pragma unroll 8
+    for (int j = j0; j < js; ++j, up += p.vlen) {
+      const double2 uj = *reinterpret_cast<const double2*>(up);
+      s.x += wrow[j] * uj.x;
+      s.y += wrow[j] * uj.y;
+    }
+    if (j1 == k) {
+      const double2 uj = ld2(ulast, off);
+      s.x += wrow[k - 1] * uj.x;
+      s.y += wrow[k - 1] * uj.y;
+    }
+    st2(P + size_t(c) * p.vlen, off, s);
+  }
+}
+
 // SOE helper workgroup `hr` of nh: for steps k = k0..k1 it advances the
 // history F^{(k)} = e^{-s tau_k} F^{(k-1)} + theta_k (u^{k-1} - u^{k-2}) over its
 // slice of the elements and forms the next level's history sum
@@ -603,6 +648,15 @@ __device__ __forceinline__ int helper_loop(const Prob& p, int hr, int k0, int k1
         __hip_atomic_store(p.hflag + size_t(h) * 64, unsigned(k), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else if (!wait_ge<127>(p, myflag, unsigned(k), ctl)) {
       return FIDS_EDEVICE;
+    }
+    if (p.history == FIDS_HISTORY_DIRECT) {
+      direct_helper_step(p, hr, k);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(&p.sync2[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      continue;
     }
     const bool next = k + 1 <= p.M;
     for (int j = threadIdx.x; j < nexp; j += kThreads) {
@@ -736,10 +790,19 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
         double2 dsum = make_double2(0.0, 0.0);   // direct scheme: sum_{k<m} w_k u^k
         if (direct) {
           dsum = make_double2(dw[m - 1] * a1.x, dw[m - 1] * a1.y);
-          for (int k = 0; k < m - 1; ++k) {
-            const double2 uk = ld2(p.uhist + size_t(k) * p.vlen, off);
-            dsum.x += dw[k] * uk.x;
-            dsum.y += dw[k] * uk.y;
+          if (p.nh > 0 && m >= 3) {          // the helpers' chunks of sum_{k<m-1} w_k u^k
+            const double* P = p.dpart + size_t(m & 1) * size_t(p.djc) * p.vlen + off;
+            for (int c = 0; c < p.djc; ++c) {
+              const double2 s = *reinterpret_cast<const double2*>(P + size_t(c) * p.vlen);
+              dsum.x += s.x;
+              dsum.y += s.y;
+            }
+          } else {
+            for (int k = 0; k < m - 1; ++k) {
+              const double2 uk = ld2(p.uhist + size_t(k) * p.vlen, off);
+              dsum.x += dw[k] * uk.x;
+              dsum.y += dw[k] * uk.y;
+            }
           }
           if (m >= 2) {
             const double2 a2 = ld2(um2, off);
@@ -1925,6 +1988,8 @@ __global__ void __launch_bounds__(kThreads) k_to_natural(const Prob* pp, const d
   const Prob& p = *pp;
   const Plan& pl = p.pl;
   const int tile = blockIdx.x;
+  src += size_t(blockIdx.y) * p.vlen;
+  dst += size_t(blockIdx.y) * p.n;
   const TileIdx t = tile_idx(pl, tile);
   for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
     int i0, sl;
@@ -2066,9 +2131,16 @@ hipError_t launch_init_state(const Prob& h, const Prob* d, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_to_natural(const Prob& h, const Prob* d, const double* src, double* dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_natural, dim3(h.pl.ntiles), dim3(kThreads), 0, s, d, src, dst);
-  return hipGetLastError();
+hipError_t launch_to_natural(const Prob& h, const Prob* d, const double* src, double* dst, hipStream_t s,
+                             int64_t count) {
+  for (int64_t k0 = 0; k0 < count; k0 += 65535) {
+    const unsigned c = unsigned(std::min<int64_t>(65535, count - k0));
+    hipLaunchKernelGGL(k_to_natural, dim3(h.pl.ntiles, c), dim3(kThreads), 0, s, d,
+                       src + size_t(k0) * h.vlen, dst + size_t(k0) * h.n);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_from_natural(const Prob& h, const Prob* d, const double* src, double* dst, hipStream_t s) {

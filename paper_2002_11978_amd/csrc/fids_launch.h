@@ -50,6 +50,8 @@ hipError_t set_level_lds_limit(const Prob& h, size_t bytes);
 hipError_t launch_from_natural(const Prob& h, const Prob* d, const double* src, double* dst, hipStream_t s);
 
 // Copies u^m (tile-major) into a natural-layout [n] array.
-hipError_t launch_to_natural(const Prob& h, const Prob* d, const double* src, double* dst, hipStream_t s);
+// count vectors: src + k * vlen (tile-major) -> dst + k * n (natural), k < count
+hipError_t launch_to_natural(const Prob& h, const Prob* d, const double* src, double* dst, hipStream_t s,
+                             int64_t count = 1);
 
 }  // namespace fids

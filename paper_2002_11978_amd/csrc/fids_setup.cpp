@@ -7,6 +7,7 @@
 #include <limits>
 #include <map>
 #include <mutex>
+#include <thread>
 
 namespace fids {
 
@@ -85,13 +86,22 @@ std::vector<double> direct_history_weights(double T, int64_t M, double r, double
   const std::vector<double> tau = step_sizes(T, M, r);
   const double g = 1.0 / std::tgamma(1.0 - gamma);
   std::vector<double> w(size_t(M) * size_t(M + 1) / 2, 0.0);
-  for (int64_t m = 1; m <= M; ++m) {
-    const std::vector<double> a = l1_row(T, M, r, gamma, m, tau);
-    double* row = w.data() + size_t(m - 1) * size_t(m) / 2;
-    // b^m = g [a_1 u^0 + sum_{k=1}^{m-1} (a_{k+1} - a_k) u^k] + f^m  (eq. 4.1)
-    row[0] = g * a[1];
-    for (int64_t k = 1; k <= m - 1; ++k) row[k] = g * (a[size_t(k + 1)] - a[size_t(k)]);
-  }
+  // rows are independent: interleaved over host threads (row m costs O(m))
+  const int nt = int(std::max<int64_t>(1, std::min<int64_t>(
+      {int64_t(std::max(1u, std::thread::hardware_concurrency())), 16, M / 512 + 1})));
+  auto rows = [&](int t) {
+    for (int64_t m = M - t; m >= 1; m -= nt) {
+      const std::vector<double> a = l1_row(T, M, r, gamma, m, tau);
+      double* row = w.data() + size_t(m - 1) * size_t(m) / 2;
+      // b^m = g [a_1 u^0 + sum_{k=1}^{m-1} (a_{k+1} - a_k) u^k] + f^m  (eq. 4.1)
+      row[0] = g * a[1];
+      for (int64_t k = 1; k <= m - 1; ++k) row[k] = g * (a[size_t(k + 1)] - a[size_t(k)]);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(rows, t);
+  rows(0);
+  for (auto& th : pool) th.join();
   return w;
 }
 

@@ -207,3 +207,21 @@ def test_direct_history_matches_oracle(n, M, kw):
     say(f"  direct vs oracle {ed:.3e}, fast vs oracle {ef:.3e}")
     assert ed <= (1e-7 if kw.get("precision", 0) == 1 else 1e-9)
     assert ef <= _gate(kw)
+
+
+@pytest.mark.parametrize("kw", [VARIANTS[0], VARIANTS[12]])
+@pytest.mark.parametrize("n,M,wg", [(5, 30, 0), (1000, 24, 0), (2100, 20, 0), (2100, 20, 2)])
+def test_direct_history_helpers(n, M, wg, kw):
+    """The direct history's sum over the stored states streamed by helper
+    workgroups one level ahead (chunks of the states, partials added by the
+    solver group): every helper count gives the oracle's solution, and the
+    same as the solver group summing alone up to rounding order."""
+    pb = W.seeded(1.7, 0.6, n, M, kappa_seed=71, f_seed=72)
+    R = _oracle(pb)
+    base, _ = gpu_solve(pb, soe_tol=1e-10, krylov_tol=1e-12, history=1, soe_helpers=0, wg_count=wg, **kw)
+    assert rel_maxnorm(base, R) <= 1e-9
+    for h in (1, 3, 64, -1):
+        U, _ = gpu_solve(pb, soe_tol=1e-10, krylov_tol=1e-12, history=1, soe_helpers=h, wg_count=wg, **kw)
+        e, eb = rel_maxnorm(U, R), rel_maxnorm(U, base)
+        say(f"  helpers {h}: vs oracle {e:.3e}, vs no helpers {eb:.3e}")
+        assert e <= 1e-9 and eb <= 1e-11
