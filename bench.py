@@ -10,11 +10,13 @@ Krylov solve.  The timed region starts from level 0 (inputs resident in HBM,
 set-up tables built) and runs exactly --steps levels, restarting from level 0
 after level M; it includes the per-level symbol construction.
 
-Three forms of the same scheme are measured (more with --forms):
-  headline  flexible GMRES(20), FP64, initial guess by cubic extrapolation
+Four forms of the same scheme are measured (more with --forms):
+  headline  preconditioned conjugate gradients on the symmetrised system
+            K^{-1} M (Sec. 4.2), FP64, initial guess by cubic extrapolation
+  fgmres    flexible GMRES(20), FP64, the same initial guess
   plain     BiCGSTAB, FP64, zero initial guess (the paper's solver settings)
   mixed     flexible GMRES(20) with the preconditioner FFTs in FP32
-  linear_x0, quad_x0  the headline form with linear / quadratic extrapolation
+  linear_x0, quad_x0  the fgmres form with linear / quadratic extrapolation
 `value` is the headline form; the others are reported beside it together with
 the relative difference of their u(T) from the headline's.
 
@@ -43,7 +45,8 @@ import numpy as np
 HBM_PEAK_GBS = 8000.0
 
 FORMS = {
-    "headline": dict(solver=1, precision=0, x0_mode=3, label="fgmres(20)-fp64-x0cubic"),
+    "headline": dict(solver=2, precision=0, x0_mode=3, label="pcg-symmetrised-fp64-x0cubic"),
+    "fgmres": dict(solver=1, precision=0, x0_mode=3, label="fgmres(20)-fp64-x0cubic"),
     "linear_x0": dict(solver=1, precision=0, x0_mode=1, label="fgmres(20)-fp64-x0linear"),
     "quad_x0": dict(solver=1, precision=0, x0_mode=2, label="fgmres(20)-fp64-x0quad"),
     "plain": dict(solver=0, precision=0, x0_mode=0, label="bicgstab-fp64-x0zero"),
@@ -59,7 +62,7 @@ def parse():
     ap.add_argument("--n", type=int, default=65535)
     ap.add_argument("--M", type=int, default=2048)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--forms", default="headline,plain,mixed")
+    ap.add_argument("--forms", default="headline,fgmres,plain,mixed")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-levels", type=int, default=100)
     ap.add_argument("--cpu-n", type=int, default=4095)
@@ -85,6 +88,11 @@ def level_bytes(form, n, nexp, iters, matvecs, restart=20):
         u^{m-2}, f^m, kappa^m read and b written (40 n);
       BiCGSTAB, per iteration (2 matvecs, 2 preconditioner applications, 7
         dot products, 4 vector updates): 280 n;
+      PCG, per iteration: P^{-1} on K^{-1} r (r, kbar/kappa, symbol read, u
+        written) 32 n, matvec with the two dots (symbol, kappa, u, r read, w
+        written) 40 n, updates of p, s, x, r (u, w, p, s, x, r read, p, s,
+        x, r written) 80 n; with an initial guess the explicit initial
+        residual (x0, symbol, kappa, b read, r and A x0 written) 48 n;
       FGMRES, Arnoldi step j (0-based within a cycle): matvec 32 n, P^{-1}
         apply 24 n, dots with v_0..v_j 8 n (j+1), forming z_{j+1} and v_{j+1}
         from z_0..z_j, v_0..v_j 16 n (j+1) + 24 n, re-orthogonalisation dots
@@ -94,6 +102,8 @@ def level_bytes(form, n, nexp, iters, matvecs, restart=20):
     b = 16.0 * n * nexp + 40.0 * n
     if FORMS[form]["solver"] == 0:
         return b + 140.0 * n * matvecs
+    if FORMS[form]["solver"] == 2:
+        return b + (48.0 * n if FORMS[form]["x0_mode"] else 0.0) + 152.0 * n * iters
     zb = 4.0 if FORMS[form]["precision"] == 1 else 8.0
     for i in range(iters):
         j = i % restart
@@ -143,8 +153,8 @@ def adjoint_leg(tol):
            "form": FORMS["headline"]["label"]}
     for name, extra in (("checkpoint_32", dict(checkpoint_every=32)), ("stored_states", dict(store_states=1))):
         prm = fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=pb.M, r=pb.r, soe_tol=1e-10,
-                                  krylov_tol=tol, krylov_maxit=500, kappa_time_dependent=0, solver=1, x0_mode=3,
-                                  **extra)
+                                  krylov_tol=tol, krylov_maxit=500, kappa_time_dependent=0,
+                                  solver=FORMS["headline"]["solver"], x0_mode=3, **extra)
         prob = fids.Problem(prm, k, f, phi)
         best = None
         for _ in range(2):
@@ -185,7 +195,8 @@ def batch_leg(tol, count):
                        f"alpha~U(1.1,1.9), gamma~U(0.2,0.8), r=(2-gamma)/gamma, M={M}, seeded kappa(x,t), f(x,t)",
            "count": count, "M": M}
     for name, cfg in (("fp64", dict(solver=1, precision=0, x0_mode=3, precond=2)),
-                      ("mixed", dict(solver=1, precision=1, x0_mode=3, precond=2))):
+                      ("mixed", dict(solver=1, precision=1, x0_mode=3, precond=2)),
+                      ("pcg", dict(solver=2, precision=0, x0_mode=3, precond=2))):
         params = [fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=M, r=pb.r, soe_tol=1e-10,
                                       krylov_tol=tol, krylov_maxit=500, **cfg) for pb in pbs]
         t0 = time.perf_counter()
@@ -211,8 +222,9 @@ def batch_leg(tol, count):
         out[name] = {"problem_levels_per_s": count * M / best, "solve_ms": best * 1e3, "init_s": t_init,
                      "tune_s": t_tune,
                      "avg_iters": float(its.mean()), "levels_with_fp64_pc": int((fb > 0).sum()),
-                     "form": f"fgmres(20)-{'fp64' if cfg['precision'] == 0 else 'fp64/fp32pc'}-x0cubic-"
-                             "kappa-scaled-strang"}
+                     "form": ("pcg-symmetrised-fp64-x0cubic-strang" if cfg["solver"] == 2 else
+                              f"fgmres(20)-{'fp64' if cfg['precision'] == 0 else 'fp64/fp32pc'}-x0cubic-"
+                              "kappa-scaled-strang")}
         print(f"[bench] batch {name}: {count * M / best:.0f} problem-levels/s ({best * 1e3:.1f} ms), "
               f"its {its.mean():.2f}, fp64-pc levels {(fb > 0).sum()}", file=sys.stderr, flush=True)
         b.close()

@@ -63,6 +63,14 @@ extern "C" {
 /* ------------------------------------------------------------ knobs */
 #define FIDS_BICGSTAB 0   /* right-preconditioned BiCGSTAB (the paper's solver, Sec. 5) */
 #define FIDS_FGMRES   1   /* flexible GMRES(restart), right preconditioning          */
+#define FIDS_PCG      2   /* conjugate gradients on the symmetrised system           */
+                          /* K_m^{-1} M^{(m)} = b_m' K_m^{-1} + A (SPD: K_m diagonal */
+                          /* positive, A SPD by Prop. 3.1) with the SPD            */
+                          /* preconditioner P^{(m)} / kbar_m (Sec. 4.2 names PCG   */
+                          /* for these systems); FIDS_STRANG and FIDS_STRANG_K     */
+                          /* are then the same operator, FIDS_NONE is plain CG on  */
+                          /* the symmetrised system; stops on the residual of the  */
+                          /* original system like the others; FP64 only           */
 #define FIDS_FP64     0   /* every FFT, vector and reduction in FP64                 */
 #define FIDS_MIXED    1   /* preconditioner FFTs in FP32, everything else FP64; a    */
                           /* level unconverged after one restart cycle continues   */
@@ -96,7 +104,7 @@ typedef struct fids_params {
     int32_t krylov_maxit; /* max BiCGSTAB iterations / max FGMRES inner iterations */
                           /* summed over restarts, per time level                  */
     int32_t restart;      /* FGMRES Krylov dimension J (<= 32)                     */
-    int32_t solver;       /* FIDS_BICGSTAB | FIDS_FGMRES                           */
+    int32_t solver;       /* FIDS_BICGSTAB | FIDS_FGMRES | FIDS_PCG                */
     int32_t precision;    /* FIDS_FP64 | FIDS_MIXED (MIXED needs FIDS_FGMRES)      */
     int32_t precond;      /* FIDS_STRANG | FIDS_NONE | FIDS_STRANG_K               */
     int32_t kappa_time_dependent; /* 1: kappa_d is [M][n]; 0: kappa_d is [n]      */

@@ -455,8 +455,14 @@ template <typename R> __device__ __forceinline__ Cx<R> tocx(double2 v) { return 
 // Input of a P^{-1} application: with the kappa-scaled preconditioner
 // P = K_m C_m, P^{-1} v = C_m^{-1} K_m^{-1} v, and C_m^{-1} = kbar_m (b_m' I + kbar_m s(A))^{-1}
 // reuses the Strang symbol, so v is scaled by kbar_m / kappa_i^m (dsc, tile-major).
+// Conjugate gradients apply the same operator to the original residual r: the
+// symmetrised system's residual is K_m^{-1} r and its preconditioner
+// P^{(m)} / kbar_m, so z = kbar_m (b_m' I + kbar_m s(A))^{-1} K_m^{-1} r.
+__device__ __forceinline__ bool kscaled(const Prob& p) {
+  return p.precond == FIDS_STRANG_K || p.solver == FIDS_PCG;
+}
 __device__ __forceinline__ double2 pc_in(const Prob& p, int off, double2 v) {
-  if (p.precond != FIDS_STRANG_K) return v;
+  if (!kscaled(p)) return v;
   const double2 d = *reinterpret_cast<const double2*>(p.dsc + off);
   return make_double2(v.x * d.x, v.y * d.y);
 }
@@ -755,7 +761,7 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
   const double* fm = p.f + size_t(m - 1) * p.n;
   const double* km = p.kappa + (p.kappa_td ? size_t(m - 1) * p.n : 0);
   const double* H1m = p.H1 + size_t(m & 1) * p.vlen;
-  const bool kscale = p.precond == FIDS_STRANG_K;
+  const bool kscale = kscaled(p);
   const double kb = kscale ? p.kbar[m] : 0.0;
   // extrapolation: npts earlier states u^{m-1}, ..., u^{m-npts} with weights w[]
   // (the fused residual also needs their stored A u^{m-k}, kept from level 1 on)
@@ -993,7 +999,7 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
     extrap_weights(d, npts, w);
   }
   const double* km = p.kappa + (p.kappa_td ? size_t(m - 1) * p.n : 0);
-  const bool kscale = p.precond == FIDS_STRANG_K;
+  const bool kscale = kscaled(p);
   const double kb = kscale ? p.kbar[m] : 0.0;
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
@@ -1403,6 +1409,148 @@ __device__ __forceinline__ int level_bicgstab(const Prob& p, int m, int rank, Ct
       return FIDS_ENOCONV;
     }
     rho = rho_new;
+  }
+}
+
+// ------------------------------------------------------------- PCG
+// Conjugate gradients on the symmetrised system S = K_m^{-1} M^{(m)} =
+// b_m' K_m^{-1} + A (SPD) with right-hand side K_m^{-1} b and preconditioner
+// C = P^{(m)} / kbar_m, in the one-reduction form of Chronopoulos and Gear
+// (the recurrences for p and s = S p share one reduction of the two dots per
+// iteration).  The vectors kept are those of the original system: r = b -
+// M x (= K_m times the symmetrised residual), u = C^{-1} K_m^{-1} r, w = M u
+// and s = M p, so every inner product of the symmetrised system carries the
+// weight 1/kappa: (r_s, u) = sum r u / kappa, (S u, u) = sum w u / kappa.
+// Per iteration: rows of P^{-1} | C pass -> u, A pass of A on u | rows of A |
+// C pass -> w, dots | updates of p, s, x, r, A pass of P^{-1} on r: five
+// group barriers, one matvec, one preconditioner application.
+
+// C pass of A on u: w = b_m' u + kappa .* A u; partials (r,u)_K, (w,u)_K.
+__device__ __forceinline__ void pcg_C_matvec(const Prob& p, int m, int rank, const Lds& L) {
+  const Plan& pl = L.pl;
+  const double inv = 1.0 / double(pl.Nc);
+  const double bm = p.beta[m];
+  for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
+    const TileIdx t = tile_idx(pl, tile);
+    tileC_load_ifft<double>(pl, tile, p.T, L.bd);
+    double acc[2] = {0.0, 0.0};
+    for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
+      int i0, sl;
+      item(pl, t, idx, i0, sl);
+      if (i0 >= p.n) continue;
+      const int off = t.toff + 2 * idx;
+      const double2 y = cscale<double>(L.bd[sl], inv);
+      const double2 u = ld2(p.vec[VPH], off), kk = ld2(p.kap, off), r = ld2(p.vec[VR], off);
+      const double2 w = mask2(make_double2(bm * u.x + kk.x * y.x, bm * u.y + kk.y * y.y), i0, p.n);
+      st2(p.vec[VV], off, w);
+      const double ix = 1.0 / kk.x, iy = i0 + 1 < p.n ? 1.0 / kk.y : 0.0;
+      acc[0] += (r.x * u.x) * ix + (r.y * u.y) * iy;
+      acc[1] += (w.x * u.x) * ix + (w.y * u.y) * iy;
+    }
+    const int sl[2] = {SL_RS, SL_TS};
+    write_partials<2>(p, tile, sl, acc);
+  }
+}
+
+// p = u + beta p, s = w + beta s (first iteration: p = u, s = w);
+// x += alpha p, r -= alpha s; partial (r,r); A pass of P^{-1} on r.
+__device__ __forceinline__ void pcg_update(const Prob& p, int m, int rank, double alpha, double beta, bool first,
+                                           const Lds& L) {
+  const Plan& pl = L.pl;
+  double* x = p.u[m % kRing];
+  for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
+    const TileIdx t = tile_idx(pl, tile);
+    double acc[1] = {0.0};
+    for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
+      int i0, sl;
+      item(pl, t, idx, i0, sl);
+      const int off = t.toff + 2 * idx;
+      double2 r = make_double2(0.0, 0.0);
+      if (i0 < p.n) {
+        double2 pp = ld2(p.vec[VPH], off), ss = ld2(p.vec[VV], off);
+        if (!first) {
+          const double2 po = ld2(p.vec[VP], off), so = ld2(p.vec[VS], off);
+          pp = make_double2(pp.x + beta * po.x, pp.y + beta * po.y);
+          ss = make_double2(ss.x + beta * so.x, ss.y + beta * so.y);
+        }
+        st2(p.vec[VP], off, pp);
+        st2(p.vec[VS], off, ss);
+        double2 xx = ld2(x, off);
+        xx.x += alpha * pp.x;
+        xx.y += alpha * pp.y;
+        st2(x, off, mask2(xx, i0, p.n));
+        r = ld2(p.vec[VR], off);
+        r = mask2(make_double2(r.x - alpha * ss.x, r.y - alpha * ss.y), i0, p.n);
+        st2(p.vec[VR], off, r);
+        acc[0] += r.x * r.x + r.y * r.y;
+        r = pc_in(p, off, r);
+      }
+      L.bd[sl] = r;
+    }
+    const int sl[1] = {SL_RR};
+    write_partials<1>(p, tile, sl, acc);
+    tileA_fft_store<double>(pl, tile, L.bd, p.T);
+  }
+}
+
+// One level of FIDS with preconditioned conjugate gradients.
+__device__ __forceinline__ int level_pcg(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L) {
+  const double* Q = pQ<double>(p, m);
+  const double tol = p.tol;
+  double bb, rr;
+  {
+    const int st = level_start(p, m, rank, ctl, L, false, bb, rr);
+    if (st != FIDS_OK) return st;
+  }
+  if (bad(bb) || bad(rr)) { write_info(p, rank, m, 0, 0, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
+  const double bnorm = sqrt(bb);
+  int it = 0, mv = p.x0_mode != 0 ? 1 : 0;
+  if (sqrt(rr) <= tol * bnorm) {
+    write_info(p, rank, m, 0, mv, bnorm > 0 ? sqrt(rr) / bnorm : 0.0, FIDS_OK);
+    return FIDS_OK;
+  }
+  double alpha = 0.0, gamma_old = 0.0;
+  for (;;) {
+    phase_rows<double, double>(p, rank, Q, p.T, L.bd, L);   // P^{-1} r
+    BARRIER();
+    bi_C_then_A(p, rank, VPH, L);                        // u ; A u (column pass)
+    BARRIER();
+    phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd, L);
+    BARRIER();
+    pcg_C_matvec(p, m, rank, L);                         // w = M u ; (r,u)_K, (w,u)_K
+    BARRIER();
+    ++mv;
+    double red2[2];
+    {
+      const int sl[2] = {SL_RS, SL_TS};
+      reduce_slots<2>(p, sl, red2);
+    }
+    const double g = red2[0], d = red2[1];
+    if (bad(g) || bad(d)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
+    const double beta = it == 0 ? 0.0 : g / gamma_old;
+    const double den = it == 0 ? d : d - beta * g / alpha;
+    // S and C are SPD: g > 0 and den = (p, S p) > 0 unless r = 0 or rounding took over
+    if (!(g > 0.0) || !(den > 0.0)) {
+      write_info(p, rank, m, it, mv, sqrt(rr) / bnorm, FIDS_ENOCONV);
+      return FIDS_ENOCONV;
+    }
+    alpha = g / den;
+    gamma_old = g;
+    pcg_update(p, m, rank, alpha, beta, it == 0, L);     // p, s, x, r ; P^{-1} r (column pass)
+    BARRIER();
+    ++it;
+    double red1[1];
+    {
+      const int sl[1] = {SL_RR};
+      reduce_slots<1>(p, sl, red1);
+    }
+    rr = red1[0];
+    if (bad(rr)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
+    if (sqrt(rr) <= tol * bnorm) { write_info(p, rank, m, it, mv, sqrt(rr) / bnorm, FIDS_OK); return FIDS_OK; }
+    if (it >= p.maxit) {
+      write_info(p, rank, m, it, mv, sqrt(rr) / bnorm, FIDS_ENOCONV);
+      return FIDS_ENOCONV;
+    }
   }
 }
 
@@ -1818,11 +1966,12 @@ __device__ __forceinline__ int level_fgmres(const Prob& p, int m, int rank, Ctl&
 
 // Level solver variants; each kernel instance holds one, so that its register
 // allocation follows that path alone.
-enum { VAR_BICG = 0, VAR_GM64 = 1, VAR_GM32 = 2, VAR_COUNT = 3 };
+enum { VAR_BICG = 0, VAR_GM64 = 1, VAR_GM32 = 2, VAR_PCG = 3, VAR_COUNT = 4 };
 
 template <int VAR>
 __device__ __forceinline__ int level_solve(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L) {
   if constexpr (VAR == VAR_BICG) return level_bicgstab(p, m, rank, ctl, L);
+  else if constexpr (VAR == VAR_PCG) return level_pcg(p, m, rank, ctl, L);
   else if constexpr (VAR == VAR_GM32) return level_fgmres<float>(p, m, rank, ctl, L);
   else return level_fgmres<double>(p, m, rank, ctl, L);
 }
@@ -2177,8 +2326,11 @@ static const void* level_kernel(const Prob& h) {
   static const void* const table[VAR_COUNT][2] = {
       {reinterpret_cast<const void*>(k_levels<VAR_BICG, false>), reinterpret_cast<const void*>(k_levels<VAR_BICG, true>)},
       {reinterpret_cast<const void*>(k_levels<VAR_GM64, false>), reinterpret_cast<const void*>(k_levels<VAR_GM64, true>)},
-      {reinterpret_cast<const void*>(k_levels<VAR_GM32, false>), reinterpret_cast<const void*>(k_levels<VAR_GM32, true>)}};
-  const int var = h.solver == FIDS_BICGSTAB ? VAR_BICG : (h.precision == FIDS_MIXED ? VAR_GM32 : VAR_GM64);
+      {reinterpret_cast<const void*>(k_levels<VAR_GM32, false>), reinterpret_cast<const void*>(k_levels<VAR_GM32, true>)},
+      {reinterpret_cast<const void*>(k_levels<VAR_PCG, false>), reinterpret_cast<const void*>(k_levels<VAR_PCG, true>)}};
+  const int var = h.solver == FIDS_BICGSTAB ? VAR_BICG
+                  : h.solver == FIDS_PCG    ? VAR_PCG
+                                            : (h.precision == FIDS_MIXED ? VAR_GM32 : VAR_GM64);
   return table[var][h.adjoint ? 1 : 0];
 }
 

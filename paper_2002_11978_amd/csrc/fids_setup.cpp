@@ -24,7 +24,7 @@ int validate(const fids_params& p) {
   if (!(p.l > 0) || !(p.T > 0)) return FIDS_EINVAL;
   if (!(p.soe_tol > 0 && p.soe_tol < 1) || !(p.krylov_tol > 0 && p.krylov_tol < 1)) return FIDS_EINVAL;
   if (p.krylov_maxit < 1 || p.restart < 1 || p.restart > 32) return FIDS_EINVAL;
-  if (p.solver != FIDS_BICGSTAB && p.solver != FIDS_FGMRES) return FIDS_EINVAL;
+  if (p.solver != FIDS_BICGSTAB && p.solver != FIDS_FGMRES && p.solver != FIDS_PCG) return FIDS_EINVAL;
   if (p.precision != FIDS_FP64 && p.precision != FIDS_MIXED) return FIDS_EINVAL;
   if (p.precision == FIDS_MIXED && p.solver != FIDS_FGMRES) return FIDS_EINVAL;
   if (p.precond != FIDS_STRANG && p.precond != FIDS_NONE && p.precond != FIDS_STRANG_K) return FIDS_EINVAL;

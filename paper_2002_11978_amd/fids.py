@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libfids.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "fids.h")
 
 FIDS_OK, FIDS_EINVAL, FIDS_EDEVICE, FIDS_ENOCONV, FIDS_ENUMERIC, FIDS_ESTATE = 0, -1, -2, -3, -4, -5
-FIDS_BICGSTAB, FIDS_FGMRES = 0, 1
+FIDS_BICGSTAB, FIDS_FGMRES, FIDS_PCG = 0, 1, 2
 FIDS_FP64, FIDS_MIXED = 0, 1
 FIDS_STRANG, FIDS_NONE, FIDS_STRANG_K = 0, 1, 2
 FIDS_HISTORY_SOE, FIDS_HISTORY_DIRECT = 0, 1

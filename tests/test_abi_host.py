@@ -40,6 +40,15 @@ def test_invalid_parameters_rejected(field, value):
     assert fids.lib().fids_workspace_size(ctypes.byref(p), ctypes.byref(sz)) == fids.FIDS_EINVAL
 
 
+def test_solver_precision_combinations():
+    sz = ctypes.c_size_t(0)
+    for solver, precision, ok in [(0, 0, True), (1, 0, True), (2, 0, True), (1, 1, True),
+                                  (0, 1, False), (2, 1, False), (3, 0, False)]:
+        p = fids.default_params(solver=solver, precision=precision)
+        st = fids.lib().fids_workspace_size(ctypes.byref(p), ctypes.byref(sz))
+        assert (st == fids.FIDS_OK) == ok, (solver, precision, st)
+
+
 def test_null_pointers_rejected():
     L = fids.lib()
     p = fids.default_params()

@@ -29,6 +29,7 @@ VARIANTS = [
     pytest.param(dict(solver=1, precision=0, x0_mode=0), id="fgmres-fp64-x0zero"),
     pytest.param(dict(solver=1, precision=0, x0_mode=1), id="fgmres-fp64-x0extrap"),
     pytest.param(dict(solver=1, precision=1, x0_mode=1), id="fgmres-mixed-x0extrap"),
+    pytest.param(dict(solver=2, precision=0, x0_mode=3), id="pcg-fp64-x0cubic"),
 ]
 
 

@@ -54,7 +54,8 @@ def _mixed_members(M):
 
 
 @pytest.mark.parametrize("kw", [dict(solver=0, precision=0, x0_mode=0), dict(solver=1, precision=0, x0_mode=1),
-                                MIXED], ids=["bicgstab-fp64", "fgmres-fp64", "fgmres-mixed"])
+                                MIXED, dict(solver=2, precision=0, x0_mode=3)],
+                         ids=["bicgstab-fp64", "fgmres-fp64", "fgmres-mixed", "pcg-fp64"])
 def test_batch_members_equal_solo_and_oracle(kw):
     pbs = _mixed_members(12)
     b = _batch(pbs, **kw)

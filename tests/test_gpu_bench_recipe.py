@@ -21,7 +21,8 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_recipe_n4095_M2048_uT.txt")
 
 FORMS = [
-    pytest.param(dict(solver=1, precision=0, x0_mode=3), 1e-8, id="headline-fgmres-fp64-x0cubic"),
+    pytest.param(dict(solver=2, precision=0, x0_mode=3), 1e-8, id="headline-pcg-fp64-x0cubic"),
+    pytest.param(dict(solver=1, precision=0, x0_mode=3), 1e-8, id="fgmres-fp64-x0cubic"),
     pytest.param(dict(solver=0, precision=0, x0_mode=0), 1e-8, id="plain-bicgstab-fp64"),
     pytest.param(dict(solver=1, precision=1, x0_mode=3), 1e-7, id="mixed-fgmres-fp32pc-x0cubic"),
     pytest.param(dict(solver=1, precision=0, x0_mode=3, precond=2), 1e-8, id="fgmres-fp64-kpc"),

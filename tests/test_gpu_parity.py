@@ -36,6 +36,9 @@ VARIANTS = [
     pytest.param(dict(solver=1, precision=1, x0_mode=2, precond=2), id="fgmres-mixed-x0quad-kpc"),
     pytest.param(dict(solver=0, precision=0, x0_mode=3), id="bicgstab-fp64-x0cubic"),
     pytest.param(dict(solver=1, precision=0, x0_mode=3), id="fgmres-fp64-x0cubic"),
+    pytest.param(dict(solver=2, precision=0, x0_mode=0), id="pcg-fp64-x0zero"),
+    pytest.param(dict(solver=2, precision=0, x0_mode=3), id="pcg-fp64-x0cubic"),
+    pytest.param(dict(solver=2, precision=0, x0_mode=1, precond=2), id="pcg-fp64-x0extrap-kpc"),
 ]
 
 
@@ -225,3 +228,36 @@ def test_direct_history_helpers(n, M, wg, kw):
         e, eb = rel_maxnorm(U, R), rel_maxnorm(U, base)
         say(f"  helpers {h}: vs oracle {e:.3e}, vs no helpers {eb:.3e}")
         assert e <= 1e-9 and eb <= 1e-11
+
+
+def test_pcg_preconditioner_forms():
+    """Conjugate gradients on the symmetrised system K^{-1} M (Sec. 4.2):
+    the Strang and the kappa-scaled Strang preconditioner are one operator
+    there (P / kbar applied to K^{-1} r), so the two runs agree bit for bit;
+    without a preconditioner (plain CG) the answer is the same and the
+    iterations many more."""
+    pb = W.seeded(1.6, 0.5, 700, 10, kappa_seed=81, f_seed=82)
+    R = _oracle(pb)
+    U0, r0 = gpu_solve(pb, soe_tol=1e-10, krylov_tol=1e-12, solver=2, precond=0)
+    U2, _ = gpu_solve(pb, soe_tol=1e-10, krylov_tol=1e-12, solver=2, precond=2)
+    Ui, ri = gpu_solve(pb, soe_tol=1e-10, krylov_tol=1e-12, solver=2, precond=1, krylov_maxit=3000)
+    assert np.array_equal(U0, U2)
+    e0, ei = rel_maxnorm(U0, R), rel_maxnorm(Ui, R)
+    its0, itsi = np.mean([r.iters for r in r0]), np.mean([r.iters for r in ri])
+    say(f"  PCG vs oracle {e0:.3e} ({its0:.1f} its), CG {ei:.3e} ({itsi:.1f} its)")
+    assert e0 <= 1e-8 and ei <= 1e-8
+    assert itsi > 3 * its0
+
+
+def test_pcg_kappa_of_t_only():
+    """kappa(x, t) = kappa(t) (the setting of the spectral analysis of Sec. 4.2,
+    where M^{(m)} itself is SPD): PCG converges in few iterations and matches
+    the oracle."""
+    pb = W.seeded(1.5, 0.4, 1023, 12, kappa_seed=83, f_seed=84)
+    pb.kappa = np.repeat((1.0 + 0.5 * np.sin(np.arange(1, pb.M + 1)))[:, None], pb.n, axis=1).copy()
+    R = _oracle(pb)
+    U, reps = gpu_solve(pb, soe_tol=1e-10, krylov_tol=1e-12, solver=2, x0_mode=3)
+    e = rel_maxnorm(U, R)
+    its = np.mean([r.iters for r in reps])
+    say(f"  kappa(t): PCG vs oracle {e:.3e}, {its:.1f} its")
+    assert e <= 1e-8 and its <= 15
