@@ -371,6 +371,8 @@ def measured_traffic(n, M):
         return None
     if t.get("kernel_sha256") != sha or t.get("n") != n or t.get("M") != M:
         return None
+    if not str(t.get("form", "")).startswith(FORMS["headline"]["label"]):
+        return None
     return t
 
 
