@@ -125,11 +125,16 @@ def test_soe_helpers(kw, helpers):
     assert err <= _gate(kw)
 
 
-def test_step_by_step_with_helpers_matches_solve_all():
+@pytest.mark.parametrize("kw", [dict(solver=1, precision=0, x0_mode=1, soe_helpers=8, wg_count=4),
+                                dict(solver=2, precision=0, x0_mode=3, soe_helpers=8, wg_count=4, history=1),
+                                dict(solver=0, precision=0, x0_mode=0, soe_helpers=-1, history=1)],
+                         ids=["soe-helpers", "direct-helpers-pcg", "direct-auto-helpers-bicgstab"])
+def test_step_by_step_with_helpers_matches_solve_all(kw):
+    """One launch per level (fids_step) gives the states of one launch for
+    all levels bit for bit, with the history streamed by helper workgroups."""
     from paper_2002_11978_amd import fids
     from gpu_util import to_dev
     pb = W.seeded(1.6, 0.4, 2047, 12, kappa_seed=3, f_seed=4)
-    kw = dict(solver=1, precision=0, x0_mode=1, soe_helpers=8, wg_count=4)
     U1, _ = gpu_solve(pb, **kw)
     params = fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=pb.M, r=pb.r, **kw)
     prob = fids.Problem(params, to_dev(pb.kappa), to_dev(pb.f), to_dev(pb.phi))
