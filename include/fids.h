@@ -267,9 +267,8 @@ int fids_batch_groups(const fids_batch* b, int32_t* ng);
 /* Host-only: the placement fids_batch_init would choose on `resident`
  * co-resident workgroups.  ng[i] is member i's group size and slot[i] its
  * slot (members of a one-workgroup slot run in turn); *makespan (may be NULL)
- * is the modelled time of one level of the slowest slot in microseconds
- * (a member on one workgroup is modelled from level times measured on
- * MI355X, which grow slowly with n: small members are latency-bound). */
+ * is the modelled cost of the slowest slot, in units of one level of a
+ * length-1 embedding on one workgroup. */
 int fids_batch_plan(const fids_params* p, int32_t count, int32_t resident, int32_t* ng, int32_t* slot,
                     double* makespan);
 

@@ -610,29 +610,12 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
 }
 
 // ---------------------------------------------------------------- batch helpers
-// Modelled time of one level of a member on one workgroup, in microseconds.
-// Such a member is latency-bound: its 40-60 passes per level cost nearly the
-// same from L = 4096 to 32768.  Measured on MI355X (PCG, cubic x0, tol 1e-10,
-// 9-12 iterations per level): 192, 460, 613, 686, 756 us for L = 2^10, 2^12,
-// 2^13, 2^14, 2^15 (2^11 interpolated); beyond 2^15 proportional to L.
-double level_cost_us(int64_t L) {
-  static const double t[6] = {192.0, 330.0, 460.0, 613.0, 686.0, 756.0};   // log2 L = 10..15
-  const int q = ilog2i(L);
-  if (q <= 10) return t[0];
-  if (q <= 15) return t[q - 10];
-  return t[5] * double(L >> 15);
-}
-
-// Modelled level time of a member of one-workgroup cost c on a group of k
-// workgroups.  Up to L = 2^15 the split gains little (measured: n = 16383 on
-// 2 workgroups 0.759 ms against 0.756 on one; n = 4095 on 4 workgroups 1.39x
-// faster): c / k^0.25.  Longer embeddings split well, less about 50 group
-// barriers per level at 1.5 us + 70 ns per workgroup: c / k^0.8 + 75 + 3.5 k.
-double group_cost(double c, int k, int64_t L) {
-  if (k <= 1) return c;
-  if (L <= (int64_t(1) << 15)) return c / std::pow(double(k), 0.25);
-  return c / std::pow(double(k), 0.8) + 75.0 + 3.5 * k;
-}
+// Work of one level of a member, in units of the embedding length L (the
+// passes stream O(L) data each), and the extra cost of a group of k > 1
+// workgroups (about 50 group barriers per level at 1.5 us + 70 ns per
+// workgroup, which is worth about 260 + 12 k units at 0.29 us per unit on
+// one workgroup).
+double group_cost(double c, int k) { return c / k + (k > 1 ? 260.0 + 12.0 * k : 0.0); }
 
 // Schedule of a batch on R co-resident workgroups: members whose cost
 // exceeds the makespan target T get a group of k > 1 workgroups (powers of
@@ -644,15 +627,15 @@ struct Slot {
   std::vector<int> members;
 };
 
-bool schedule_at(double T, const std::vector<double>& c, const std::vector<int>& kmax,
-                 const std::vector<int64_t>& Ls, int R, std::vector<Slot>* out) {
+bool schedule_at(double T, const std::vector<double>& c, const std::vector<int>& kmax, int R,
+                 std::vector<Slot>* out) {
   std::vector<Slot> slots;
   std::vector<int> small;
   int total = 0;
   for (size_t i = 0; i < c.size(); ++i) {
     if (c[i] <= T) { small.push_back(int(i)); continue; }
     int k = 2;
-    while (k <= kmax[i] && group_cost(c[i], k, Ls[i]) > T) k *= 2;
+    while (k <= kmax[i] && group_cost(c[i], k) > T) k *= 2;
     if (k > kmax[i]) return false;
     slots.push_back({k, {int(i)}});
     total += k;
@@ -679,49 +662,45 @@ bool schedule_at(double T, const std::vector<double>& c, const std::vector<int>&
   return true;
 }
 
-std::vector<Slot> schedule_batch(const std::vector<double>& c, const std::vector<int>& kmax,
-                                 const std::vector<int64_t>& Ls, int R) {
+std::vector<Slot> schedule_batch(const std::vector<double>& c, const std::vector<int>& kmax, int R) {
   double lo = 0.0, hi = 0.0;
   for (size_t i = 0; i < c.size(); ++i) {
     double best = c[i];
-    for (int k = 2; k <= kmax[i]; k *= 2) best = std::min(best, group_cost(c[i], k, Ls[i]));
+    for (int k = 2; k <= kmax[i]; k *= 2) best = std::min(best, group_cost(c[i], k));
     lo = std::max(lo, best);
     hi += c[i];
   }
   std::vector<Slot> out;
-  if (!schedule_at(hi, c, kmax, Ls, R, &out)) {
+  if (!schedule_at(hi, c, kmax, R, &out)) {
     // fewer workgroups than needed even with everything packed: one slot
     out.assign(1, {1, {}});
     for (size_t i = 0; i < c.size(); ++i) out[0].members.push_back(int(i));
     return out;
   }
-  if (schedule_at(lo, c, kmax, Ls, R, &out)) return out;
+  if (schedule_at(lo, c, kmax, R, &out)) return out;
   for (int it = 0; it < 60; ++it) {
     const double mid = 0.5 * (lo + hi);
-    if (schedule_at(mid, c, kmax, Ls, R, nullptr)) hi = mid;
+    if (schedule_at(mid, c, kmax, R, nullptr)) hi = mid;
     else lo = mid;
   }
-  schedule_at(hi, c, kmax, Ls, R, &out);
+  schedule_at(hi, c, kmax, R, &out);
   return out;
 }
 
-// Per-member cost (modelled level time on one workgroup, level_cost_us), its
-// embedding length L, largest useful group (powers of two,
+// Per-member cost (embedding length L), largest useful group (powers of two,
 // at least 1024 packed points per workgroup, at most 64) and, optionally, a
 // bound on the level kernel's LDS (one-workgroup plans have the largest tiles)
 // with a descriptor for the occupancy query.
 int batch_costs(const fids_params* p, int32_t count, std::vector<double>& cost, std::vector<int>& kmax,
-                std::vector<int64_t>& Ls, size_t* lds_bound, Prob* probe) {
+                size_t* lds_bound, Prob* probe) {
   cost.assign(size_t(count), 0.0);
   kmax.assign(size_t(count), 1);
-  Ls.assign(size_t(count), 0);
   for (int32_t i = 0; i < count; ++i) {
     fids_params q = p[i];
     batch_params(q, 1);
     Shapes sh;
     if (shapes_of(q, sh, nullptr) != FIDS_OK) return FIDS_EINVAL;
-    cost[size_t(i)] = level_cost_us(sh.L);
-    Ls[size_t(i)] = sh.L;
+    cost[size_t(i)] = double(sh.L);
     int k = 1;
     while (k * 2 <= std::min(64, sh.pr.N2) && int64_t(k) * 2 * 1024 <= sh.Nc) k *= 2;
     kmax[size_t(i)] = k;
@@ -999,8 +978,7 @@ int fids_batch_init(const fids_params* p, int32_t count, const double* const* ka
   std::vector<int> kmax;
   size_t lds_bound = 0;
   Prob probe{};
-  std::vector<int64_t> Ls;
-  if (batch_costs(p, count, cost, kmax, Ls, &lds_bound, &probe) != FIDS_OK) return fail(FIDS_EINVAL);
+  if (batch_costs(p, count, cost, kmax, &lds_bound, &probe) != FIDS_OK) return fail(FIDS_EINVAL);
   int resident = count;
   {
     int dev = 0, cus = 0, per_cu = 0;
@@ -1012,7 +990,7 @@ int fids_batch_init(const fids_params* p, int32_t count, const double* const* ka
       return fail(FIDS_EDEVICE);
     resident = std::max(1, cus * per_cu);
   }
-  const std::vector<Slot> slots = schedule_batch(cost, kmax, Ls, resident);
+  const std::vector<Slot> slots = schedule_batch(cost, kmax, resident);
   b->hprobs.resize(size_t(count));
   b->members.assign(size_t(count), nullptr);
   b->groups.assign(size_t(count), 1);
@@ -1155,16 +1133,15 @@ int fids_batch_plan(const fids_params* p, int32_t count, int32_t resident, int32
   if (!p || count < 1 || resident < 1 || !ng || !slot) return FIDS_EINVAL;
   std::vector<double> cost;
   std::vector<int> kmax;
-  std::vector<int64_t> Ls;
-  if (batch_costs(p, count, cost, kmax, Ls, nullptr, nullptr) != FIDS_OK) return FIDS_EINVAL;
-  const std::vector<Slot> slots = schedule_batch(cost, kmax, Ls, resident);
+  if (batch_costs(p, count, cost, kmax, nullptr, nullptr) != FIDS_OK) return FIDS_EINVAL;
+  const std::vector<Slot> slots = schedule_batch(cost, kmax, resident);
   double worst = 0.0;
   for (size_t k = 0; k < slots.size(); ++k) {
     double load = 0.0;
     for (int i : slots[k].members) {
       ng[i] = slots[k].ng;
       slot[i] = int32_t(k);
-      load += group_cost(cost[size_t(i)], slots[k].ng, Ls[size_t(i)]);
+      load += group_cost(cost[size_t(i)], slots[k].ng);
     }
     worst = std::max(worst, load);
   }

@@ -135,23 +135,6 @@ def _embed(n):
     return L
 
 
-# the scheduler's model: level time of a member on one workgroup (us) and on
-# a group of k workgroups
-_T1 = {10: 192.0, 11: 330.0, 12: 460.0, 13: 613.0, 14: 686.0, 15: 756.0}
-
-
-def _cost1(n):
-    q = _embed(n).bit_length() - 1
-    return _T1[max(10, q)] if q <= 15 else 756.0 * 2 ** (q - 15)
-
-
-def _costk(n, k):
-    c, L = _cost1(n), _embed(n)
-    if k == 1:
-        return c
-    return c / k ** 0.25 if L <= 2 ** 15 else c / k ** 0.8 + 75 + 3.5 * k
-
-
 @pytest.mark.parametrize("resident", [1, 7, 64, 256, 1024])
 def test_batch_plan_is_a_valid_placement(resident):
     """Every member is placed once; groups of more than one workgroup hold one
@@ -171,28 +154,22 @@ def test_batch_plan_is_a_valid_placement(resident):
             assert len(members) == 1
         used += k
     assert used <= max(resident, 1)
-    best = [min(_costk(p.n, k) for k in (1, 2, 4, 8, 16, 32, 64) if k == 1 or k * 1024 <= _embed(p.n) // 2)
-            for p in ps]
-    # workgroup-time of a member: k c_k on a group of k
-    area = sum(min(k * _costk(p.n, k) for k in (1, 2, 4, 8, 16, 32, 64) if k == 1 or k * 1024 <= _embed(p.n) // 2)
-               for p in ps) / resident
-    assert mk >= max(best) - 1e-9
+    cost = [_embed(p.n) for p in ps]
     if resident >= 2:
-        assert mk >= area - 1e-9
-    if resident == len(ps):
-        # as many workgroups as members: no groups (they gain little at these
-        # sizes), the slowest member alone sets the makespan
-        assert ng == [1] * len(ps)
-        assert mk == pytest.approx(max(_cost1(p.n) for p in ps))
-    elif resident >= 64:
-        assert mk <= 1.5 * max(area, max(best))
+        assert mk >= sum(cost) / resident - 1e-9
+    assert mk >= max(c / 64 for c in cost)
+    if resident >= 64:
+        lower = max(sum(cost) / resident, max(min(c / k + (260 + 12 * k if k > 1 else 0)
+                                                  for k in (1, 2, 4, 8, 16, 32, 64) if k * 1024 <= c // 2 or k == 1)
+                                              for c in cost))
+        assert mk <= 1.5 * lower
 
 
 def test_batch_plan_single_workgroup_packs_everything():
     ps = _batch_params(12)
     ng, slot, mk = fids.batch_plan(ps, 1)
     assert ng == [1] * 12 and len(set(slot)) == 1
-    assert mk == pytest.approx(sum(_cost1(p.n) for p in ps))
+    assert mk == pytest.approx(sum(_embed(p.n) for p in ps))
 
 
 @pytest.mark.parametrize("M,r,gamma,m", [(25268, 3.0, 0.8, 25268), (25268, 3.0, 0.8, 9000),
