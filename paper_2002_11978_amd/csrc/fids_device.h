@@ -18,6 +18,9 @@ constexpr int kThreads = 512;     // threads per workgroup in every kernel
 constexpr int kMaxFFT = 4096;     // longest per-workgroup FFT (complex points)
 constexpr int kMaxRestart = 32;
 constexpr int kRing = 4;          // states kept: u^m lives in u[m % kRing] (and A u^m in AU)
+constexpr int kSoeBatch = 8;      // SOE nodes whose history values are loaded together
+constexpr int kLoadBatch = 4;     // column-pass loads per thread issued together
+constexpr int kVecBatch = 2;      // solver element items per thread whose loads are issued together
 constexpr int kMaxHelpers = 1024; // helper workgroups (one release-flag line each)
 constexpr int kDirectChunks = 128; // direct history: most state chunks per element block
 

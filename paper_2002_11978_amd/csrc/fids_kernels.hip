@@ -144,9 +144,22 @@ __device__ __forceinline__ void tileC_load_ifft(const Plan& pl, int tile, const 
   const int c0 = tile * pl.CT, logCT = ilog2(pl.CT);
   const int total = pl.CT * pl.N1;
   __syncthreads();
-  for (int idx = threadIdx.x; idx < total; idx += kThreads) {
-    const int c = idx & (pl.CT - 1), k1 = idx >> logCT;
-    buf[c * pl.N1 + k1] = T[k1 * pl.N2 + c0 + c];
+  // kLoadBatch loads per thread in flight before their LDS stores (both are
+  // generic pointers, so the compiler keeps a load behind an earlier store)
+  for (int base = threadIdx.x; base < total; base += kLoadBatch * kThreads) {
+    R vx[kLoadBatch], vy[kLoadBatch];
+#pragma unroll
+    for (int q = 0; q < kLoadBatch; ++q) {
+      const int idx = min(base + q * kThreads, total - 1);   // in range; stored only below total
+      const Cx<R> v = T[(idx >> logCT) * pl.N2 + c0 + (idx & (pl.CT - 1))];
+      vx[q] = v.x;
+      vy[q] = v.y;
+    }
+#pragma unroll
+    for (int q = 0; q < kLoadBatch; ++q) {
+      const int idx = base + q * kThreads;
+      if (idx < total) buf[(idx & (pl.CT - 1)) * pl.N1 + (idx >> logCT)] = mk<R>(vx[q], vy[q]);
+    }
   }
   __syncthreads();
   const Cx<R>* res = lds_fft<R>(buf, buf + total, pl.N1, pl.log1, pl.CT, +1, tw_n1<R>(pl));
@@ -825,7 +838,26 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
           if (self_soe) {
             double* Fp = p.F + size_t(tile) * nexp * blk + 2 * idx;
             double* Fc = snap ? ck + size_t(2 * kRing) * p.vlen + size_t(tile) * nexp * blk + 2 * idx : nullptr;
-            for (int j = 0; j < nexp; ++j) {
+            // the loads of kSoeBatch nodes are issued together: a store to F_j
+            // would otherwise hold back the load of F_{j+1} (same base
+            // pointer), one memory round trip per node; same arithmetic order
+            int j = 0;
+            for (; j + kSoeBatch <= nexp; j += kSoeBatch) {
+              double2 fb[kSoeBatch];
+#pragma unroll
+              for (int q = 0; q < kSoeBatch; ++q) fb[q] = ld2(Fp, (j + q) * blk);
+#pragma unroll
+              for (int q = 0; q < kSoeBatch; ++q) {
+                double2 fj = fb[q];
+                if (snap) st2(Fc, (j + q) * blk, fj);
+                fj.x = de[j + q] * fj.x + th[j + q] * d.x;
+                fj.y = de[j + q] * fj.y + th[j + q] * d.y;
+                st2(Fp, (j + q) * blk, fj);
+                h.x += gw[j + q] * fj.x;
+                h.y += gw[j + q] * fj.y;
+              }
+            }
+            for (; j < nexp; ++j) {
               double2 fj = ld2(Fp, j * blk);
               if (snap) st2(Fc, j * blk, fj);
               fj.x = de[j] * fj.x + th[j] * d.x;
@@ -1095,7 +1127,24 @@ __device__ __forceinline__ void phase_adj_post(const Prob& p, int m, int rank, c
         if (m >= 2) {
           double* Fp = p.F + size_t(tile) * nexp * blk + 2 * idx;
           double2 r = make_double2(0.0, 0.0);
-          for (int j = 0; j < nexp; ++j) {
+          int j = 0;
+          for (; j + kSoeBatch <= nexp; j += kSoeBatch) {   // loads issued together (see phase_rhs)
+            double2 fv[kSoeBatch];
+#pragma unroll
+            for (int q = 0; q < kSoeBatch; ++q) fv[q] = ld2(Fp, (j + q) * blk);
+#pragma unroll
+            for (int q = 0; q < kSoeBatch; ++q) {
+              double2 fb = fv[q];
+              fb.x -= gw[j + q] * lm.x;
+              fb.y -= gw[j + q] * lm.y;
+              r.x += th[j + q] * fb.x;
+              r.y += th[j + q] * fb.y;
+              fb.x *= de[j + q];
+              fb.y *= de[j + q];
+              st2(Fp, (j + q) * blk, fb);
+            }
+          }
+          for (; j < nexp; ++j) {
             double2 fb = ld2(Fp, j * blk);
             fb.x -= gw[j] * lm.x;
             fb.y -= gw[j] * lm.y;
@@ -1434,18 +1483,35 @@ __device__ __forceinline__ void pcg_C_matvec(const Prob& p, int m, int rank, con
     const TileIdx t = tile_idx(pl, tile);
     tileC_load_ifft<double>(pl, tile, p.T, L.bd);
     double acc[2] = {0.0, 0.0};
-    for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
-      int i0, sl;
-      item(pl, t, idx, i0, sl);
-      if (i0 >= p.n) continue;
-      const int off = t.toff + 2 * idx;
-      const double2 y = cscale<double>(L.bd[sl], inv);
-      const double2 u = ld2(p.vec[VPH], off), kk = ld2(p.kap, off), r = ld2(p.vec[VR], off);
-      const double2 w = mask2(make_double2(bm * u.x + kk.x * y.x, bm * u.y + kk.y * y.y), i0, p.n);
-      st2(p.vec[VV], off, w);
-      const double ix = 1.0 / kk.x, iy = i0 + 1 < p.n ? 1.0 / kk.y : 0.0;
-      acc[0] += (r.x * u.x) * ix + (r.y * u.y) * iy;
-      acc[1] += (w.x * u.x) * ix + (w.y * u.y) * iy;
+    for (int base = threadIdx.x; base < t.total; base += kVecBatch * kThreads) {
+      double2 uu[kVecBatch], kv[kVecBatch], rv[kVecBatch];
+#pragma unroll
+      for (int q = 0; q < kVecBatch; ++q) {   // loads first (see pcg_update)
+        const int idx = base + q * kThreads;
+        int i0, sl;
+        item(pl, t, idx, i0, sl);
+        const int off = t.toff + 2 * idx;
+        if (idx < t.total && i0 < p.n) {
+          uu[q] = ld2(p.vec[VPH], off);
+          kv[q] = ld2(p.kap, off);
+          rv[q] = ld2(p.vec[VR], off);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kVecBatch; ++q) {
+        const int idx = base + q * kThreads;
+        int i0, sl;
+        item(pl, t, idx, i0, sl);
+        if (idx >= t.total || i0 >= p.n) continue;
+        const int off = t.toff + 2 * idx;
+        const double2 y = cscale<double>(L.bd[sl], inv);
+        const double2 u = uu[q], kk = kv[q], r = rv[q];
+        const double2 w = mask2(make_double2(bm * u.x + kk.x * y.x, bm * u.y + kk.y * y.y), i0, p.n);
+        st2(p.vec[VV], off, w);
+        const double ix = 1.0 / kk.x, iy = i0 + 1 < p.n ? 1.0 / kk.y : 0.0;
+        acc[0] += (r.x * u.x) * ix + (r.y * u.y) * iy;
+        acc[1] += (w.x * u.x) * ix + (w.y * u.y) * iy;
+      }
     }
     const int sl[2] = {SL_RS, SL_TS};
     write_partials<2>(p, tile, sl, acc);
@@ -1461,31 +1527,53 @@ __device__ __forceinline__ void pcg_update(const Prob& p, int m, int rank, doubl
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
     double acc[1] = {0.0};
-    for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
-      int i0, sl;
-      item(pl, t, idx, i0, sl);
-      const int off = t.toff + 2 * idx;
-      double2 r = make_double2(0.0, 0.0);
-      if (i0 < p.n) {
-        double2 pp = ld2(p.vec[VPH], off), ss = ld2(p.vec[VV], off);
-        if (!first) {
-          const double2 po = ld2(p.vec[VP], off), so = ld2(p.vec[VS], off);
-          pp = make_double2(pp.x + beta * po.x, pp.y + beta * po.y);
-          ss = make_double2(ss.x + beta * so.x, ss.y + beta * so.y);
+    // kVecBatch items per thread: all loads first (the stores to the same
+    // vectors would otherwise hold back the next item's loads)
+    for (int base = threadIdx.x; base < t.total; base += kVecBatch * kThreads) {
+      double2 uu[kVecBatch], ww[kVecBatch], po[kVecBatch], so[kVecBatch], xo[kVecBatch], ro[kVecBatch];
+      double2 dd[kVecBatch];
+#pragma unroll
+      for (int q = 0; q < kVecBatch; ++q) {
+        const int idx = base + q * kThreads;
+        int i0, sl;
+        item(pl, t, idx, i0, sl);
+        const int off = t.toff + 2 * idx;
+        if (idx < t.total && i0 < p.n) {
+          uu[q] = ld2(p.vec[VPH], off);
+          ww[q] = ld2(p.vec[VV], off);
+          if (!first) { po[q] = ld2(p.vec[VP], off); so[q] = ld2(p.vec[VS], off); }
+          xo[q] = ld2(x, off);
+          ro[q] = ld2(p.vec[VR], off);
+          dd[q] = ld2(p.dsc, off);
         }
-        st2(p.vec[VP], off, pp);
-        st2(p.vec[VS], off, ss);
-        double2 xx = ld2(x, off);
-        xx.x += alpha * pp.x;
-        xx.y += alpha * pp.y;
-        st2(x, off, mask2(xx, i0, p.n));
-        r = ld2(p.vec[VR], off);
-        r = mask2(make_double2(r.x - alpha * ss.x, r.y - alpha * ss.y), i0, p.n);
-        st2(p.vec[VR], off, r);
-        acc[0] += r.x * r.x + r.y * r.y;
-        r = pc_in(p, off, r);
       }
-      L.bd[sl] = r;
+#pragma unroll
+      for (int q = 0; q < kVecBatch; ++q) {
+        const int idx = base + q * kThreads;
+        if (idx >= t.total) continue;
+        int i0, sl;
+        item(pl, t, idx, i0, sl);
+        const int off = t.toff + 2 * idx;
+        double2 r = make_double2(0.0, 0.0);
+        if (i0 < p.n) {
+          double2 pp = uu[q], ss = ww[q];
+          if (!first) {
+            pp = make_double2(pp.x + beta * po[q].x, pp.y + beta * po[q].y);
+            ss = make_double2(ss.x + beta * so[q].x, ss.y + beta * so[q].y);
+          }
+          st2(p.vec[VP], off, pp);
+          st2(p.vec[VS], off, ss);
+          double2 xx = xo[q];
+          xx.x += alpha * pp.x;
+          xx.y += alpha * pp.y;
+          st2(x, off, mask2(xx, i0, p.n));
+          r = mask2(make_double2(ro[q].x - alpha * ss.x, ro[q].y - alpha * ss.y), i0, p.n);
+          st2(p.vec[VR], off, r);
+          acc[0] += r.x * r.x + r.y * r.y;
+          r = make_double2(r.x * dd[q].x, r.y * dd[q].y);   // pc_in: PCG always scales by kbar / kappa
+        }
+        L.bd[sl] = r;
+      }
     }
     const int sl[1] = {SL_RR};
     write_partials<1>(p, tile, sl, acc);
