@@ -91,8 +91,9 @@ def level_bytes(form, n, nexp, iters, matvecs, restart=20):
       PCG, per iteration: P^{-1} on K^{-1} r (r, kbar/kappa, symbol read, u
         written) 32 n, matvec with the two dots (symbol, kappa, u, r read, w
         written) 40 n, updates of p, s, x, r (u, w, p, s, x, r read, p, s,
-        x, r written) 80 n; with an initial guess the explicit initial
-        residual (x0, symbol, kappa, b read, r and A x0 written) 48 n;
+        x, r written) 80 n; per level the true residual of the result (x,
+        symbol, kappa, b read, r and A x written) 48 n, and with an initial
+        guess the same for its initial residual;
       FGMRES, Arnoldi step j (0-based within a cycle): matvec 32 n, P^{-1}
         apply 24 n, dots with v_0..v_j 8 n (j+1), forming z_{j+1} and v_{j+1}
         from z_0..z_j, v_0..v_j 16 n (j+1) + 24 n, re-orthogonalisation dots
@@ -103,7 +104,8 @@ def level_bytes(form, n, nexp, iters, matvecs, restart=20):
     if FORMS[form]["solver"] == 0:
         return b + 140.0 * n * matvecs
     if FORMS[form]["solver"] == 2:
-        return b + (48.0 * n if FORMS[form]["x0_mode"] else 0.0) + 152.0 * n * iters
+        checks = max(1, matvecs - iters - (1 if FORMS[form]["x0_mode"] else 0))   # true-residual passes
+        return b + (48.0 * n if FORMS[form]["x0_mode"] else 0.0) + 48.0 * n * checks + 152.0 * n * iters
     zb = 4.0 if FORMS[form]["precision"] == 1 else 8.0
     for i in range(iters):
         j = i % restart

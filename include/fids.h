@@ -70,7 +70,11 @@ extern "C" {
                           /* for these systems); FIDS_STRANG and FIDS_STRANG_K     */
                           /* are then the same operator, FIDS_NONE is plain CG on  */
                           /* the symmetrised system; stops on the residual of the  */
-                          /* original system like the others; FP64 only           */
+                          /* original system like the others, then verifies it by  */
+                          /* an explicit matvec (a true residual above 4 x tol     */
+                          /* restarts CG; a level whose true residual stalls is    */
+                          /* accepted at that FP64 floor, its true value reported  */
+                          /* in fids_step_info.relres); FP64 only                 */
 #define FIDS_FP64     0   /* every FFT, vector and reduction in FP64                 */
 #define FIDS_MIXED    1   /* preconditioner FFTs in FP32, everything else FP64; a    */
                           /* level unconverged after one restart cycle continues   */

@@ -108,6 +108,7 @@ struct BatchLayout {
 struct Shapes {
   int64_t n, M, L, Nc;
   int nexp;
+  int grp;                // workgroups the problem's group may use
   PlanShape pr, pc, ps;   // level plan, Bluestein (complex L) plan, symbol (real) plan
 };
 
@@ -208,6 +209,7 @@ int shapes_of(const fids_params& p, Shapes& sh, fids::SoeNodes* soe_out) {
   if (fids::soe_build(p.gamma, tau1, p.T, p.soe_tol, soe) != FIDS_OK) return FIDS_EINVAL;
   sh.nexp = int(soe.s.size());
   const int grp = p.wg_count > 0 ? p.wg_count : env_int("FIDS_WG", default_group(sh.Nc));
+  sh.grp = std::max(1, grp);
   // column tiles default to one per workgroup; FIDS_TILES overrides (tuning)
   const int skew = env_int("FIDS_SKEW", 0);
   sh.pr = plan_shape(sh.Nc, env_int("FIDS_TILES", grp), grp, skew);
@@ -331,15 +333,28 @@ int upload(fids_problem* h, size_t off, const void* src, size_t bytes) {
 }
 
 void fill_plan(Plan& pl, const PlanShape& s, int rootmul, char* ws, const Layout& lo, bool complex_plan) {
+  pl.twres = 0;
   pl.Nc = s.Nc; pl.N1 = s.N1; pl.N2 = s.N2; pl.log1 = s.log1; pl.log2 = s.log2; pl.CT = s.CT;
   pl.ntiles = s.ntiles; pl.nunits = s.nunits; pl.RU = s.RU; pl.nrg = s.nrg; pl.rootmul = rootmul;
   pl.twshift = lo.twshift; pl.twmask = (1 << lo.twshift) - 1;
+  pl.twn = fids::lds_twiddles(pl, s.Nc * rootmul);
   pl.tw1 = at<double2>(ws, complex_plan ? lo.tw1c : lo.tw1r);
   pl.tw1f = at<float2>(ws, complex_plan ? lo.tw1cf : lo.tw1rf);
   pl.tw2 = at<double2>(ws, complex_plan ? lo.tw2c : lo.tw2r);
   pl.tw2f = at<float2>(ws, complex_plan ? lo.tw2cf : lo.tw2rf);
   pl.twlo = at<double2>(ws, lo.twlo); pl.twlof = at<float2>(ws, lo.twlof);
   pl.twhi = at<double2>(ws, lo.twhi); pl.twhif = at<float2>(ws, lo.twhif);
+}
+
+// The first twiddle residency (all tables in LDS, then the root tables out,
+// then all out) whose level-kernel LDS fits `cap`.
+int fit_lds(Prob& hp, size_t cap) {
+  for (int r = 0; r <= 2; ++r) {
+    hp.pl.twres = r;
+    hp.pl.twn = fids::lds_twiddles(hp.pl, hp.L);
+    if (fids::level_lds_bytes(hp) <= cap) return FIDS_OK;
+  }
+  return FIDS_EDEVICE;
 }
 
 int ensure_symbols(fids_problem* h) {
@@ -496,7 +511,10 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   fill_plan(hp.pl, h->sh.pr, 2, ws, lo, false);
   hp.g0 = 0;
   hp.slot_first = 0;
-  hp.ng = std::max(hp.pl.ntiles, hp.pl.nrg);
+  // one workgroup per column tile or row group, up to the group size (a
+  // workgroup runs several tiles in turn where the LDS tile cap forces more
+  // tiles than that; sums stay per tile, so the result does not depend on ng)
+  hp.ng = std::max(1, std::min(std::max(hp.pl.ntiles, hp.pl.nrg), h->sh.grp));
   hp.soec = at<double>(ws, lo.soec);
   hp.H1 = at<double>(ws, lo.H1);
   hp.AU = at<double>(ws, lo.AU);
@@ -541,6 +559,17 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   j.qhat = const_cast<double*>(hp.qhat); j.qhatf = const_cast<float*>(hp.qhatf);
   j.identity = p->precond == FIDS_NONE;
   h->dj = at<SymJob>(ws, lo.job);
+  {
+    // long transforms: leave twiddle tables in global memory until the
+    // tiles and tables fit the LDS (Plan::twres)
+    size_t cap = 0;
+    if (hip_bad(fids::level_lds_cap(hp, &cap), __LINE__)) return fail(FIDS_EDEVICE);
+    if (fit_lds(hp, cap) != FIDS_OK) {
+      std::snprintf(g_last_error, sizeof(g_last_error), "fids_api.cpp:%d: level kernel needs %zu bytes of LDS (%zu available)",
+                    __LINE__, fids::level_lds_bytes(hp), cap);
+      return fail(FIDS_EDEVICE);
+    }
+  }
   h->lds = fids::level_lds_bytes(hp);
   if (batch) {
     hp.ng = batch_group;
@@ -709,6 +738,9 @@ int batch_costs(const fids_params* p, int32_t count, std::vector<double>& cost, 
       probe->pl.CT = sh.pr.CT; probe->pl.N1 = sh.pr.N1; probe->pl.N2 = sh.pr.N2; probe->pl.RU = sh.pr.RU;
       const int tws = (ilog2i(sh.L) + 1) / 2;
       probe->pl.twshift = tws; probe->pl.twmask = (1 << tws) - 1;
+      size_t cap = 0;
+      if (fids::level_lds_cap(*probe, &cap) != hipSuccess) return FIDS_EDEVICE;
+      if (fit_lds(*probe, cap) != FIDS_OK) return FIDS_EDEVICE;
       *lds_bound = std::max(*lds_bound, fids::level_lds_bytes(*probe));
     }
   }

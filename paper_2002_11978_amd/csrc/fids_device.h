@@ -20,6 +20,8 @@ constexpr int kMaxRestart = 32;
 constexpr int kRing = 4;          // states kept: u^m lives in u[m % kRing] (and A u^m in AU)
 constexpr int kSoeBatch = 8;      // SOE nodes whose history values are loaded together
 constexpr int kLoadBatch = 4;     // column-pass loads per thread issued together
+constexpr int kPcgChecks = 3;     // true-residual checks of a PCG level
+constexpr double kPcgSlack = 4.0; // PCG accepts a true residual up to this many tolerances
 constexpr int kVecBatch = 2;      // solver element items per thread whose loads are issued together
 constexpr int kMaxHelpers = 1024; // helper workgroups (one release-flag line each)
 constexpr int kDirectChunks = 128; // direct history: most state chunks per element block
@@ -49,11 +51,22 @@ struct Plan {
   int rootmul;       // W_Nc = W_root^rootmul (2 for the real-packed plan, 1 complex)
   int twshift;       // split of the root table: j = (jh << twshift) + jl
   int twmask;
+  int twres;         // twiddle tables copied to LDS: 0 all, 1 W_N1 and W_N2 only (the root
+                     // tables stay in global memory), 2 none (long transforms whose tables
+                     // and tiles do not fit the LDS together)
+  int twn;           // twiddle values that copy holds (set with twres)
   const double2* tw1;  const float2* tw1f;   // W_{N1}^j, j < N1 (e^{-2 pi i j/N1})
   const double2* tw2;  const float2* tw2f;   // W_{N2}^j
   const double2* twlo; const float2* twlof;  // W_root^{jl}
   const double2* twhi; const float2* twhif;  // W_root^{jh << twshift}
 };
+
+// Twiddle values a launch copies to LDS (see Plan::twres).
+inline int lds_twiddles(const Plan& pl, int L) {
+  if (pl.twres >= 2) return 0;
+  if (pl.twres == 1) return pl.N1 + pl.N2;
+  return pl.N1 + pl.N2 + (pl.twmask + 1) + (L >> pl.twshift);
+}
 
 // Per-problem descriptor, in device memory.
 struct Prob {

@@ -1334,6 +1334,11 @@ __device__ __forceinline__ int level_start(const Prob& p, int m, int rank, Ctl& 
                                            double& bb, double& rr0) {
   // the helpers' history sum H1^m (step m-1) must be complete
   if (p.nh > 0 && m >= 3 && !wait_ge<8>(p, &p.sync2[0], unsigned(m - 2) * unsigned(p.nh), ctl)) return FIDS_EDEVICE;
+  // FGMRES ends every level with A u^m from an explicit matvec, so the
+  // residual of an extrapolated guess can be formed from the kept products.
+  // PCG forms it by a matvec: its recurrences carry the initial residual's
+  // rounding to the end, and the extrapolation weights (4, -6, 4, -1 for the
+  // cubic) amplify that of the kept products several-fold.
   const bool fused = p.solver == FIDS_FGMRES && p.x0_mode != 0 && m >= 3 && !p.adjoint;
   if (p.adjoint) {
     if (fp32pc) phase_adj_rhs<float>(p, m, rank, L, ctl);
@@ -1581,7 +1586,29 @@ __device__ __forceinline__ void pcg_update(const Prob& p, int m, int rank, doubl
   }
 }
 
-// One level of FIDS with preconditioned conjugate gradients.
+// Column pass of A on the iterate x (the first pass of its true residual).
+__device__ __forceinline__ void pcg_x_colA(const Prob& p, int m, int rank, const Lds& L) {
+  const Plan& pl = L.pl;
+  const double* x = p.u[m % kRing];
+  for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
+    const TileIdx t = tile_idx(pl, tile);
+    for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
+      int i0, sl;
+      item(pl, t, idx, i0, sl);
+      L.bd[sl] = ld2(x, t.toff + 2 * idx);
+    }
+    tileA_fft_store<double>(pl, tile, L.bd, p.T);
+  }
+}
+
+// One level of FIDS with preconditioned conjugate gradients.  When the
+// recursively updated residual meets the tolerance, the true residual
+// b - M x is formed by an explicit matvec.  A true residual within kPcgSlack times the
+// tolerance is accepted (the gap of a few tolerances is FP64 rounding: at
+// n = 65535 every solver's true residual floor is about 2.5e-10 of ||b||);
+// beyond that CG restarts from it (at most kPcgChecks times) and a level whose
+// true residual stops improving is accepted at that attainable floor.  The
+// true value is reported either way.
 __device__ __forceinline__ int level_pcg(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L) {
   const double* Q = pQ<double>(p, m);
   const double tol = p.tol;
@@ -1592,12 +1619,13 @@ __device__ __forceinline__ int level_pcg(const Prob& p, int m, int rank, Ctl& ct
   }
   if (bad(bb) || bad(rr)) { write_info(p, rank, m, 0, 0, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
   const double bnorm = sqrt(bb);
-  int it = 0, mv = p.x0_mode != 0 ? 1 : 0;
+  int it = 0, mv = p.x0_mode != 0 ? 1 : 0;   // the residual of an extrapolated guess costs a matvec
   if (sqrt(rr) <= tol * bnorm) {
     write_info(p, rank, m, 0, mv, bnorm > 0 ? sqrt(rr) / bnorm : 0.0, FIDS_OK);
     return FIDS_OK;
   }
-  double alpha = 0.0, gamma_old = 0.0;
+  double alpha = 0.0, gamma_old = 0.0, rr_true_prev = INFINITY;
+  int cyc0 = 0, checks = 0;                // first iteration of the current CG cycle
   for (;;) {
     phase_rows<double, double>(p, rank, Q, p.T, L.bd, L);   // P^{-1} r
     BARRIER();
@@ -1615,8 +1643,9 @@ __device__ __forceinline__ int level_pcg(const Prob& p, int m, int rank, Ctl& ct
     }
     const double g = red2[0], d = red2[1];
     if (bad(g) || bad(d)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
-    const double beta = it == 0 ? 0.0 : g / gamma_old;
-    const double den = it == 0 ? d : d - beta * g / alpha;
+    const bool first = it == cyc0;
+    const double beta = first ? 0.0 : g / gamma_old;
+    const double den = first ? d : d - beta * g / alpha;
     // S and C are SPD: g > 0 and den = (p, S p) > 0 unless r = 0 or rounding took over
     if (!(g > 0.0) || !(den > 0.0)) {
       write_info(p, rank, m, it, mv, sqrt(rr) / bnorm, FIDS_ENOCONV);
@@ -1624,17 +1653,34 @@ __device__ __forceinline__ int level_pcg(const Prob& p, int m, int rank, Ctl& ct
     }
     alpha = g / den;
     gamma_old = g;
-    pcg_update(p, m, rank, alpha, beta, it == 0, L);     // p, s, x, r ; P^{-1} r (column pass)
+    pcg_update(p, m, rank, alpha, beta, first, L);       // p, s, x, r ; P^{-1} r (column pass)
     BARRIER();
     ++it;
     double red1[1];
-    {
-      const int sl[1] = {SL_RR};
-      reduce_slots<1>(p, sl, red1);
-    }
+    const int sl1[1] = {SL_RR};
+    reduce_slots<1>(p, sl1, red1);
     rr = red1[0];
     if (bad(rr)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
-    if (sqrt(rr) <= tol * bnorm) { write_info(p, rank, m, it, mv, sqrt(rr) / bnorm, FIDS_OK); return FIDS_OK; }
+    if (sqrt(rr) <= tol * bnorm) {
+      // true residual: A x, r = b - M x, P^{-1} column pass on r (for a restart)
+      pcg_x_colA(p, m, rank, L);
+      BARRIER();
+      phase_rows<double, double>(p, rank, p.ahat, p.T, L.bd, L);
+      BARRIER();
+      phase_r0<double>(p, m, rank, L);
+      BARRIER();
+      ++mv;
+      reduce_slots<1>(p, sl1, red1);
+      const double rt = red1[0];
+      if (bad(rt)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
+      if (sqrt(rt) <= kPcgSlack * tol * bnorm || ++checks >= kPcgChecks || !(rt < 0.25 * rr_true_prev)) {
+        write_info(p, rank, m, it, mv, sqrt(rt) / bnorm, FIDS_OK);
+        return FIDS_OK;
+      }
+      rr_true_prev = rt;
+      rr = rt;
+      cyc0 = it;                             // restart from the true residual
+    }
     if (it >= p.maxit) {
       write_info(p, rank, m, it, mv, sqrt(rr) / bnorm, FIDS_ENOCONV);
       return FIDS_ENOCONV;
@@ -2088,7 +2134,7 @@ __device__ __forceinline__ void run_member(const Prob& p, int rank, int m_begin,
   const int small_c = kSmallDoubles / 2;
   const int tile_pts = max(2 * p.pl.CT * p.pl.N1, 4 * p.pl.RU * p.pl.N2);
   const int nlo = p.pl.twmask + 1, nhi = p.L >> p.pl.twshift;
-  const int ntw = p.pl.N1 + p.pl.N2 + nlo + nhi;
+  const int ntw = p.pl.twn;               // twiddles copied to LDS (set with twres)
   const bool mixed = p.precision == FIDS_MIXED;
   Lds L;
   L.tab = reinterpret_cast<double*>(dyn);
@@ -2110,14 +2156,19 @@ __device__ __forceinline__ void run_member(const Prob& p, int rank, int m_begin,
       twd[i] = v;
       if (mixed) twf[i] = vf;
     }
-    L.pl.tw1 = twd;
-    L.pl.tw2 = twd + g.N1;
-    L.pl.twlo = twd + g.N1 + g.N2;
-    L.pl.twhi = twd + g.N1 + g.N2 + nlo;
-    L.pl.tw1f = twf;
-    L.pl.tw2f = twf + g.N1;
-    L.pl.twlof = twf + g.N1 + g.N2;
-    L.pl.twhif = twf + g.N1 + g.N2 + nlo;
+    // tables not copied keep pointing at the global ones
+    if (g.twres <= 1) {
+      L.pl.tw1 = twd;
+      L.pl.tw2 = twd + g.N1;
+      L.pl.tw1f = twf;
+      L.pl.tw2f = twf + g.N1;
+    }
+    if (g.twres == 0) {
+      L.pl.twlo = twd + g.N1 + g.N2;
+      L.pl.twhi = twd + g.N1 + g.N2 + nlo;
+      L.pl.twlof = twf + g.N1 + g.N2;
+      L.pl.twhif = twf + g.N1 + g.N2 + nlo;
+    }
     __syncthreads();
   }
   Ctl ctl;
@@ -2358,7 +2409,7 @@ size_t level_lds_bytes(const Prob& h) {
   const size_t bd = plan_lds(h.pl);
   const bool mixed = h.precision == FIDS_MIXED;
   const size_t bf = mixed ? bd / 2 : 0;
-  const size_t ntw = size_t(h.pl.N1) + h.pl.N2 + size_t(h.pl.twmask + 1) + (size_t(h.L) >> h.pl.twshift);
+  const size_t ntw = size_t(h.pl.twn);
   const size_t tw = ntw * sizeof(double2) + (mixed ? ((ntw + 1) / 2) * sizeof(double2) : 0);
   return tab + small + tw + bd + bf;
 }
@@ -2424,6 +2475,18 @@ static const void* level_kernel(const Prob& h) {
 
 hipError_t level_max_blocks(const Prob& h, size_t lds_bytes, int* per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, level_kernel(h), kThreads, lds_bytes);
+}
+
+hipError_t level_lds_cap(const Prob& h, size_t* cap) {
+  int dev = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+  hipFuncAttributes a{};
+  if (e == hipSuccess) e = hipFuncGetAttributes(&a, level_kernel(h));
+  if (e != hipSuccess) return e;
+  const size_t st = a.sharedSizeBytes;
+  *cap = size_t(per_cu) > st ? size_t(per_cu) - st : 0;
+  return hipSuccess;
 }
 
 hipError_t set_level_lds_limit(const Prob& h, size_t bytes) {

@@ -45,6 +45,9 @@ hipError_t level_max_blocks(const Prob& h, size_t lds_bytes, int* per_cu);
 
 // Raises the dynamic-LDS limit of the forward and adjoint instances of `h`'s variant.
 hipError_t set_level_lds_limit(const Prob& h, size_t bytes);
+// Dynamic LDS a level-kernel workgroup may use on the current device (the
+// CU's LDS less the kernel's static LDS).
+hipError_t level_lds_cap(const Prob& h, size_t* cap);
 
 // Natural-layout [n] array into a tile-major vector (zero padding).
 hipError_t launch_from_natural(const Prob& h, const Prob* d, const double* src, double* dst, hipStream_t s);

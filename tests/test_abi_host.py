@@ -33,6 +33,7 @@ def test_strerror_and_defaults():
     ("alpha", 0.0), ("alpha", 2.0), ("gamma", 0.0), ("gamma", 1.0), ("r", 0.5), ("n", 0), ("M", 0),
     ("l", 0.0), ("T", -1.0), ("krylov_tol", 0.0), ("soe_tol", 1.5), ("restart", 0), ("restart", 33),
     ("mu", 1.4), ("solver", 7), ("precision", 3), ("precond", 9), ("x0_mode", 4), ("soe_helpers", -2),
+    ("n", (1 << 21) + 1),
 ])
 def test_invalid_parameters_rejected(field, value):
     p = fids.default_params(**{field: value})

@@ -97,7 +97,8 @@ def test_adjoint_matches_oracle(n, M, td, kw):
 
 @pytest.mark.parametrize("kw", [VARIANTS[0], VARIANTS[3], VARIANTS[4],
                                 pytest.param(dict(solver=1, precision=0, x0_mode=2), id="fgmres-fp64-x0quad"),
-                                pytest.param(dict(solver=1, precision=0, x0_mode=3), id="fgmres-fp64-x0cubic")])
+                                pytest.param(dict(solver=1, precision=0, x0_mode=3), id="fgmres-fp64-x0cubic"),
+                                pytest.param(dict(solver=2, precision=0, x0_mode=3), id="pcg-fp64-x0cubic")])
 @pytest.mark.parametrize("C", [1, 3, 5, 16, 40])
 def test_checkpointed_equals_stored_states(C, kw):
     """Segments recomputed from snapshots give the stored-states gradients
