@@ -250,8 +250,10 @@ TABLE11 = [
 def table11_leg():
     """Example 2 at the Table 11 sizes with the paper's solver settings
     (BiCGSTAB, tol 1e-10, zero initial guess, SOE 1e-9): fast history with the
-    Strang preconditioner (FIDS+P), without it (FIDS+I), and the direct
-    history with it (DIDS+P); Err_inf against the exact solution."""
+    Strang preconditioner (FIDS+P), without it (FIDS+I), the direct history
+    with and without it (DIDS+P, DIDS+I), and FIDS+P with conjugate gradients
+    on the symmetrised system instead of BiCGSTAB; Err_inf against the exact
+    solution."""
     import torch
 
     from paper_2002_11978_amd import fids
@@ -264,14 +266,16 @@ def table11_leg():
         row = {"r": r, "gamma": g, "alpha": a, "N": Np, "M": M, "paper_err_inf": err_p, "paper_its": its_p,
                "paper_cpu_s": cpu_s}
         for name, extra in (("fids_p", dict(precond=0, history=0)), ("fids_i", dict(precond=1, history=0)),
-                            ("dids_p", dict(precond=0, history=1)), ("dids_i", dict(precond=1, history=1))):
+                            ("dids_p", dict(precond=0, history=1)), ("dids_i", dict(precond=1, history=1)),
+                            ("fids_p_pcg", dict(precond=0, history=0, solver=2))):
             # unpreconditioned runs take 100-300 iterations a level: the
             # largest rows are left out to keep the leg to a few minutes
             if extra["precond"] == 1 and M > 13000:
                 continue
+            kw = dict(solver=0, precision=0, x0_mode=0, store_states=int(extra["history"] == 0))
+            kw.update(extra)
             prm = fids.default_params(alpha=a, gamma=g, n=pb.n, M=M, r=r, soe_tol=1e-9, krylov_tol=1e-10,
-                                      krylov_maxit=2000, solver=0, precision=0, x0_mode=0,
-                                      store_states=int(extra["history"] == 0), **extra)
+                                      krylov_maxit=2000, **kw)
             prob = fids.Problem(prm, k, f, phi)
             prob.reset()
             torch.cuda.synchronize()
@@ -280,8 +284,10 @@ def table11_leg():
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             ei = float(np.max(np.abs(U.cpu().numpy() - pb.exact)))      # Err_inf = max_m ||u^m - u(t_m)||_inf
-            row[name] = {"s": dt, "levels_per_s": M / dt, "its": float(np.mean([x.matvecs for x in reps]) / 2),
-                         "err_inf": ei}
+            # the paper's Its is matvecs / 2 for BiCGSTAB; CG iterations for PCG
+            its = (np.mean([x.iters for x in reps]) if kw["solver"] == 2
+                   else np.mean([x.matvecs for x in reps]) / 2)
+            row[name] = {"s": dt, "levels_per_s": M / dt, "its": float(its), "err_inf": ei}
             prob.close()
         print(f"[bench] table11 {row}", file=sys.stderr, flush=True)
         rows.append(row)
