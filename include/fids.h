@@ -38,6 +38,19 @@
  *     kappa_time_dependent != 0, else [n]; f_d is [M][n] with row m-1 =
  *     f(x_i, t_m); phi_d and every u vector are [n]; u_all_d is [M+1][n]
  *     with row m = u^m.  All are dense row-major FP64.
+ *
+ * Tuning overrides read from the environment when a problem or batch is
+ * created (for measurement; results do not depend on them beyond rounding
+ * order, except where noted):
+ *   FIDS_WG          workgroups of a problem when wg_count = 0 (default about
+ *                    N_c / 1024, at most 64)
+ *   FIDS_TILES       column tiles of the level plan (default: the group size)
+ *   FIDS_SKEW        moves factors of two from the column FFT length to the row
+ *                    FFT length (default 0)
+ *   FIDS_HELPERS     SOE helper workgroups when soe_helpers = -1 (default 0)
+ *   FIDS_BATCH_MODE  "graph": a batch whose members all run on one workgroup
+ *                    advances by one captured HIP-graph launch per level instead
+ *                    of one persistent launch for all levels
  */
 #ifndef FIDS_H
 #define FIDS_H
