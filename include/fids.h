@@ -145,10 +145,11 @@ typedef struct fids_params {
                           /* the direct scheme (4.1), the full graded-L1 sum over */
                           /* every earlier state (keeps all states; O(m n) per    */
                           /* level; no adjoint, no batch)                         */
-    int32_t checkpoint_every; /* C > 0: the forward run snapshots its state (u^{m-1},*/
-                          /* u^{m-2}, the SOE history F^{(m-1)}) at levels         */
-                          /* m = kC + 1 and fids_adjoint recomputes each segment   */
-                          /* of C levels from its snapshot; 0: no snapshots        */
+    int32_t checkpoint_every; /* C > 0: the forward run snapshots its state         */
+                          /* (u^{m-1..m-4}, A u^{m-1..m-4}, the SOE history        */
+                          /* F^{(m-1)}) at levels m = kC + 1 and fids_adjoint      */
+                          /* recomputes each segment of C levels from its          */
+                          /* snapshot, bit for bit; 0: no snapshots                */
 } fids_params;
 
 /* Per-level report. */
