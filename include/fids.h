@@ -51,6 +51,10 @@
  *   FIDS_BATCH_MODE  "graph": a batch whose members all run on one workgroup
  *                    advances by one captured HIP-graph launch per level instead
  *                    of one persistent launch for all levels
+ *   FIDS_FLOOR_SCALE factor (default 1) on the rounding level up to which a
+ *                    stalled true residual is accepted (FIDS_LEVEL_ABOVE_TOL);
+ *                    0 accepts only residuals within 4 krylov_tol (changes
+ *                    which levels report FIDS_ENOCONV)
  */
 #ifndef FIDS_H
 #define FIDS_H
@@ -85,9 +89,10 @@ extern "C" {
                           /* the symmetrised system; stops on the residual of the  */
                           /* original system like the others, then verifies it by  */
                           /* an explicit matvec (a true residual above 4 x tol     */
-                          /* restarts CG; a level whose true residual stalls is    */
-                          /* accepted at that FP64 floor, its true value reported  */
-                          /* in fids_step_info.relres); FP64 only                 */
+                          /* restarts CG, at most 3 checks; a level whose true     */
+                          /* residual stalls is accepted at its FP64 rounding      */
+                          /* floor as described at FIDS_LEVEL_ABOVE_TOL); FP64     */
+                          /* only                                                  */
 #define FIDS_FP64     0   /* every FFT, vector and reduction in FP64                 */
 #define FIDS_MIXED    1   /* preconditioner FFTs in FP32, everything else FP64; a    */
                           /* level unconverged after one restart cycle continues   */
@@ -114,10 +119,10 @@ typedef struct fids_params {
                           /* 1 + alpha/2; kappa_mu = 2 when mu == 2 else 1         */
     double  soe_tol;      /* relative SOE tolerance on [tau_1, T] (Lemma 2.2)      */
     double  krylov_tol;   /* stop when ||b - M x||_2 <= tol ||b||_2 (BiCGSTAB: its  */
-                          /* updated residual; FGMRES: the true FP64 residual, or  */
-                          /* that residual's attainable floor -- two restart       */
-                          /* cycles whose Arnoldi estimate met tol -- with the     */
-                          /* true value reported in fids_step_info.relres)         */
+                          /* updated residual; FGMRES, PCG: the true FP64          */
+                          /* residual, or that residual's rounding floor with      */
+                          /* FIDS_LEVEL_ABOVE_TOL set -- see fids_step_info --     */
+                          /* and the true value in fids_step_info.relres)          */
     int32_t krylov_maxit; /* max BiCGSTAB iterations / max FGMRES inner iterations */
                           /* summed over restarts, per time level                  */
     int32_t restart;      /* FGMRES Krylov dimension J (<= 32)                     */
@@ -163,8 +168,19 @@ typedef struct fids_step_info {
     int32_t pc_fp64_iters;/* FIDS_MIXED: iterations run with the FP64              */
                           /* preconditioner after the first restart cycle missed   */
                           /* the tolerance (0: the level finished in FP32)         */
-    int32_t reserved;
+    int32_t flags;        /* FIDS_LEVEL_* bits                                     */
 } fids_step_info;
+
+/* fids_step_info.flags: the level was accepted with relres above krylov_tol.
+ * FGMRES and PCG check the true FP64 residual b - M x, which stagnates at a
+ * rounding level of about u log2(L) kmax_m ||A||_inf ||x|| / ||b|| (u = 2^-53,
+ * L the embedding length, kmax_m = max_i kappa(x_i, t_m)): a level whose true
+ * residual stops improving above the tolerance is accepted (FIDS_OK, this
+ * flag set) if it is within max(4 krylov_tol, that rounding level), and
+ * reported as FIDS_ENOCONV otherwise.  PCG also accepts a true residual within
+ * 4 krylov_tol without a stall.  Theorem 3.4 bounds the scheme's error by the
+ * SOE and solver tolerances, so flagged levels carry the larger residual. */
+#define FIDS_LEVEL_ABOVE_TOL 1
 
 typedef struct fids_problem fids_problem;
 
@@ -194,6 +210,17 @@ int fids_init_problem(const fids_params* p, const double* kappa_d, const double*
  * side, preconditioned Krylov solve.  u_out_d (may be NULL) receives u^{m+1};
  * info (may be NULL) the level report.  FIDS_ESTATE after level M. */
 int fids_step(fids_problem* h, double* u_out_d, fids_step_info* info);
+
+/* Advance `count` levels from the current level m (m -> m + count, each level
+ * as in fids_step) in one device launch, 1 <= count <= M - m; the per-level
+ * Strang symbols of exactly these levels are built first if they are not
+ * built yet (fids_prepare builds all of them).  u_out_d (may be NULL)
+ * receives u^{m+count}; per_step (may be NULL) is a host array of `count`
+ * entries, entry k for level m + 1 + k.  On a failed level the state stops at
+ * the last completed level, per_step holds the reports up to the failed one,
+ * and stepping again needs fids_reset.  FIDS_EINVAL for count outside that
+ * range, FIDS_ESTATE after level M. */
+int fids_solve_levels(fids_problem* h, int64_t count, double* u_out_d, fids_step_info* per_step);
 
 /* Advance from the current level to M in one device launch.  uT_d (may be
  * NULL) receives u^M; u_all_d (may be NULL; needs store_states = 1) receives
@@ -225,8 +252,9 @@ int fids_adjoint(fids_problem* h, const double* dJ_duT_d, double* g_kappa_d,
 int fids_adjoint_report(const fids_problem* h, fids_step_info* per_step);
 
 /* Back to level 0 (u^0 = phi, empty history).  Set-up tables are kept; the
- * per-level preconditioner symbols are marked stale, so the next step or
- * solve rebuilds them (every solve from level 0 includes that work). */
+ * per-level preconditioner symbols are marked stale, so each level's symbol
+ * is rebuilt by the call that next advances through it (every solve from
+ * level 0 includes that work). */
 int fids_reset(fids_problem* h);
 
 /* Builds the per-level Strang preconditioner symbols now (eq. 4.3 for every

@@ -82,7 +82,7 @@ int env_int(const char* name, int dflt) {
 // Workspace layout of one problem.  Offsets are bytes from ws_d.
 struct Layout {
   size_t prob, job, abort_, status, bar, info, part;
-  size_t beta, theta, decay, gw, ahat, lam, chirp, chirp_hat, kbar;
+  size_t beta, theta, decay, gw, ahat, lam, chirp, chirp_hat, kbar, kmax;
   size_t tw1r, tw1rf, tw2r, tw2rf, tw1c, tw1cf, tw2c, tw2cf, twlo, twlof, twhi, twhif;
   size_t qhat, qhatf;
   size_t Tb, q, Tq;
@@ -141,6 +141,7 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   lo.chirp = take(n * 16);
   lo.chirp_hat = take(L * 16);
   lo.kbar = take((M + 1) * 8);
+  lo.kmax = take((M + 1) * 8);
   lo.tw1r = take(size_t(sh.pr.N1) * 16); lo.tw1rf = take(size_t(sh.pr.N1) * 8);
   lo.tw2r = take(size_t(sh.pr.N2) * 16); lo.tw2rf = take(size_t(sh.pr.N2) * 8);
   lo.tw1c = take(size_t(sh.pc.N1) * 16); lo.tw1cf = take(size_t(sh.pc.N1) * 8);
@@ -268,7 +269,7 @@ struct fids_problem {
   int* dabort = nullptr;
   int* dstatus = nullptr;
   int64_t level = 0;
-  bool symbols_ready = false;
+  int64_t sym_hi = 0;        // per-level symbols (and kbar, kmax) valid for levels 1..sym_hi
   bool poisoned = false;     // a level failed: the state is only valid after fids_reset
   size_t lds = 0;
   unsigned long long timeout_ticks = 0;
@@ -357,18 +358,22 @@ int fit_lds(Prob& hp, size_t cap) {
   return FIDS_EDEVICE;
 }
 
-int ensure_symbols(fids_problem* h) {
-  if (h->symbols_ready) return FIDS_OK;
-  const int M = int(h->sh.M);
-  HIPCHK(fids::launch_kbar(h->prm.kappa_time_dependent ? h->hp.kappa : h->hp.kappa, int(h->sh.n), M,
-                           h->prm.kappa_time_dependent, at<double>(h->ws, h->lo.kbar), h->stream));
-  for (int m0 = 1; m0 <= M; m0 += h->lo.chunk) {
-    const int cnt = std::min(h->lo.chunk, M - m0 + 1);
-    HIPCHK(fids::launch_symbols(h->hj, h->dj, m0, cnt, h->stream));
+// Builds kbar_m, kmax_m and the per-level preconditioner symbols of levels
+// sym_hi+1..m_hi (those of earlier levels are current).
+int ensure_symbols(fids_problem* h, int64_t m_hi) {
+  m_hi = std::min<int64_t>(m_hi, h->sh.M);
+  if (h->sym_hi >= m_hi) return FIDS_OK;
+  const int a = int(h->sym_hi + 1), cnt = int(m_hi - h->sym_hi);
+  HIPCHK(fids::launch_kbar(h->hp.kappa, int(h->sh.n), a, cnt, h->prm.kappa_time_dependent,
+                           at<double>(h->ws, h->lo.kbar), at<double>(h->ws, h->lo.kmax), h->stream));
+  for (int m0 = a; m0 <= int(m_hi); m0 += h->lo.chunk) {
+    const int c = std::min(h->lo.chunk, int(m_hi) - m0 + 1);
+    HIPCHK(fids::launch_symbols(h->hj, h->dj, m0, c, h->stream));
   }
-  h->symbols_ready = true;
+  h->sym_hi = m_hi;
   return FIDS_OK;
 }
+int ensure_symbols(fids_problem* h) { return ensure_symbols(h, h->sh.M); }
 
 // One cooperative launch of the level kernel for descriptor `d` and a wait
 // for its status words {status, last completed level}.
@@ -389,9 +394,12 @@ int launch_wait(fids_problem* h, const Prob& hd, Prob* d, int m_begin, int m_end
 
 int hist_lo_of(const fids_problem* h) { return h->prm.store_states ? 0 : -1; }
 
-int run_levels(fids_problem* h, int64_t m_end, fids_step_info* infos_host /*[M] indexed m-1*/) {
+// Levels level+1..m_end in one launch (symbols of exactly those levels built
+// first); infos_host (may be NULL) receives the reports of the levels run,
+// entry k for level level+1+k.
+int run_levels(fids_problem* h, int64_t m_end, fids_step_info* infos_host) {
   if (h->level >= h->sh.M || h->poisoned) return FIDS_ESTATE;
-  int st = ensure_symbols(h);
+  int st = ensure_symbols(h, m_end);
   if (st != FIDS_OK) return st;
   const int m_begin = int(h->level + 1);
   int stat[2] = {0, 0};
@@ -401,7 +409,7 @@ int run_levels(fids_problem* h, int64_t m_end, fids_step_info* infos_host /*[M] 
   const int64_t first = m_begin;
   const int64_t upto = std::min<int64_t>(m_end, std::max<int64_t>(last + (stat[0] != FIDS_OK ? 1 : 0), first - 1));
   if (infos_host && upto >= first) {
-    HIPCHK(hipMemcpy(infos_host + (first - 1), at<fids_step_info>(h->ws, h->lo.info) + (first - 1),
+    HIPCHK(hipMemcpy(infos_host, at<fids_step_info>(h->ws, h->lo.info) + (first - 1),
                      size_t(upto - first + 1) * sizeof(fids_step_info), hipMemcpyDeviceToHost));
   }
   if (last >= first) h->level = last;
@@ -528,6 +536,17 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   for (int i = 0; i < fids::kRing; ++i) hp.u[i] = at<double>(ws, lo.u[i]);
   hp.F = at<double>(ws, lo.F); hp.kap = at<double>(ws, lo.kap); hp.dsc = at<double>(ws, lo.dsc);
   hp.kbar = at<double>(ws, lo.kbar);
+  hp.kmax = at<double>(ws, lo.kmax);
+  {
+    // ||A||_inf of the symmetric Toeplitz A: its first row's absolute sum, at most a_0 + 2 sum_{d>=1} |a_d|
+    long double a = std::fabs((long double)t.col[0]);
+    for (size_t d = 1; d < t.col.size(); ++d) a += 2.0L * std::fabs((long double)t.col[d]);
+    hp.anorm = double(a);
+  }
+  {
+    const char* fs = std::getenv("FIDS_FLOOR_SCALE");
+    hp.floor_scale = fs ? std::max(0.0, std::atof(fs)) : 1.0;
+  }
   for (int i = 0; i < 10; ++i) hp.vec[i] = at<double>(ws, lo.vec[i]);
   hp.V = lo.V ? at<double>(ws, lo.V) : nullptr;
   hp.zd = lo.Z ? at<double>(ws, lo.Z) : nullptr;
@@ -785,7 +804,6 @@ hipError_t batch_launch(fids_batch* b, int m0, int m1, hipStream_t s) {
 
 int batch_symbols(fids_batch* b) {
   for (fids_problem* h : b->members) {
-    if (h->symbols_ready) continue;
     const int st = ensure_symbols(h);
     if (st != FIDS_OK) return st;
   }
@@ -869,7 +887,7 @@ int fids_reset(fids_problem* h) {
   HIPCHK(hipStreamSynchronize(h->stream));
   h->level = 0;
   h->poisoned = false;
-  h->symbols_ready = false;  // every solve from level 0 rebuilds the per-level symbols
+  h->sym_hi = 0;  // every pass from level 0 rebuilds the per-level symbols it runs through
   return FIDS_OK;
 }
 
@@ -886,13 +904,12 @@ int fids_destroy(fids_problem* h) {
   return FIDS_OK;
 }
 
-int fids_step(fids_problem* h, double* u_out_d, fids_step_info* info) {
+int fids_solve_levels(fids_problem* h, int64_t count, double* u_out_d, fids_step_info* per_step) {
   if (!h) return FIDS_EINVAL;
   if (h->level >= h->sh.M) return FIDS_ESTATE;
-  std::vector<fids_step_info> tmp(size_t(h->sh.M));
-  const int64_t m = h->level + 1;
-  const int st = run_levels(h, m, tmp.data());
-  if (info) *info = tmp[size_t(m - 1)];
+  if (count < 1 || count > h->sh.M - h->level) return FIDS_EINVAL;
+  const int64_t m = h->level + count;
+  const int st = run_levels(h, m, per_step);
   if (st != FIDS_OK) return st;
   if (u_out_d) {
     HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.u[m % fids::kRing], u_out_d, h->stream));
@@ -901,11 +918,18 @@ int fids_step(fids_problem* h, double* u_out_d, fids_step_info* info) {
   return FIDS_OK;
 }
 
+int fids_step(fids_problem* h, double* u_out_d, fids_step_info* info) {
+  if (!h) return FIDS_EINVAL;
+  if (h->level >= h->sh.M) return FIDS_ESTATE;
+  return fids_solve_levels(h, 1, u_out_d, info);
+}
+
 int fids_solve_all(fids_problem* h, double* uT_d, double* u_all_d, fids_step_info* per_step) {
   if (!h) return FIDS_EINVAL;
   if (u_all_d && !h->prm.store_states) return FIDS_EINVAL;
   if (h->level >= h->sh.M) return FIDS_ESTATE;
-  const int st = run_levels(h, h->sh.M, per_step);
+  const int64_t first = h->level + 1;
+  const int st = run_levels(h, h->sh.M, per_step ? per_step + (first - 1) : nullptr);
   if (st != FIDS_OK) return st;
   if (uT_d) HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.u[h->sh.M % fids::kRing], uT_d, h->stream));
   if (u_all_d) HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.uhist, u_all_d, h->stream, h->sh.M + 1));
@@ -1280,6 +1304,13 @@ int fids_batch_tune(fids_batch* b, int32_t levels, int32_t* tile_ct) {
   if (b->lds > 65536) HIPCHK(fids::set_level_lds_limit(b->hprobs[0], b->lds));
   HIPCHK(hipMemcpyAsync(b->dprobs, b->hprobs.data(), b->hprobs.size() * sizeof(Prob), hipMemcpyHostToDevice,
                         b->stream));
+  // a captured level graph holds the old tiling's launch shape and LDS size:
+  // drop it so that the next solve captures the tuned one
+  if (b->graph_exec) {
+    HIPCHK(hipStreamSynchronize(b->stream));
+    (void)hipGraphExecDestroy(b->graph_exec);
+    b->graph_exec = nullptr;
+  }
   const int rs = fids_batch_reset(b);
   return st != FIDS_OK ? st : rs;
 }
@@ -1291,7 +1322,7 @@ int fids_batch_reset(fids_batch* b) {
     HIPCHK(hipMemsetAsync(h->hp.F, 0, size_t(h->hp.nexp) * h->hp.vlen * 8, b->stream));
     HIPCHK(hipMemsetAsync(h->hp.AU, 0, size_t(fids::kRing) * h->hp.vlen * 8, b->stream));
     HIPCHK(hipMemsetAsync(h->hp.bar, 0, 4 * sizeof(unsigned), b->stream));
-    h->symbols_ready = false;
+    h->sym_hi = 0;
   }
   HIPCHK(hipMemsetAsync(b->dstatus, 0, size_t(b->count) * 4 * sizeof(int), b->stream));
   HIPCHK(hipStreamSynchronize(b->stream));

@@ -37,7 +37,8 @@ inline int direct_chunks(int64_t n, int nh) {
 // Partial-sum slots (one value per column tile each).
 enum Slot {
   SL_BB = 0, SL_RV, SL_SS, SL_RS, SL_TS, SL_TT, SL_RT, SL_RR, SL_KB,
-  SL_GM = 9,                      // FGMRES: kMaxRestart + 2 consecutive slots
+  SL_XX = 9,                      // ||x||^2 of the iterate whose true residual is formed
+  SL_GM = 10,                     // FGMRES: kMaxRestart + 2 consecutive slots
   SL_COUNT = SL_GM + kMaxRestart + 2
 };
 
@@ -96,6 +97,9 @@ struct Prob {
   double* kap;                  // kappa^m, tile-major
   double* dsc;                  // kbar_m / kappa^m, tile-major (kappa-scaled preconditioner)
   const double* kbar;           // [M+1] mean of kappa^m
+  const double* kmax;           // [M+1] largest kappa^m_i (rounding level of a residual)
+  double anorm;                 // ||A||_inf = a_0 + 2 sum_{d>=1} |a_d| (first column of A)
+  double floor_scale;           // factor on the residual's rounding level (1; 0 accepts only kPcgSlack tol)
   double* vec[10];              // Krylov vectors (solver specific)
   float* zf;                    // FGMRES: Z basis in FP32 (mixed), [restart][vlen]
   double* zd;                   // FGMRES: Z basis in FP64, [restart][vlen]

@@ -557,7 +557,7 @@ __device__ __forceinline__ void write_info(const Prob& p, int rank, int m, int i
     in.matvecs = matvecs;
     in.relres = relres;
     in.pc_fp64_iters = fp64_iters;
-    in.reserved = 0;
+    in.flags = (status == FIDS_OK && relres > p.tol) ? FIDS_LEVEL_ABOVE_TOL : 0;
     p.info[m - 1] = in;
     p.status[0] = status;
     if (status == FIDS_OK) p.status[1] = m;
@@ -565,6 +565,20 @@ __device__ __forceinline__ void write_info(const Prob& p, int rank, int m, int i
 }
 
 __device__ __forceinline__ bool bad(double v) { return !isfinite(v); }
+
+// Rounding level of a true residual r = b - (b_m' x + kappa .* A x) formed in
+// FP64, relative to ||b||: a circulant product through length-L transforms
+// carries an error of about u log2(L) ||A|| ||x|| (u the unit roundoff, ||A||
+// <= ||A||_inf), scaled by kappa <= kmax_m, plus u b_m' ||x|| from the shift
+// and u ||b|| from the subtraction.  A level whose true residual stops
+// improving above the tolerance is accepted only below
+// max(kPcgSlack tol, this level); above it the level has not converged.
+__device__ __forceinline__ double floor_bound(const Prob& p, int m, double xx, double bnorm) {
+  constexpr double u = 1.1102230246251565e-16;   // 2^-53
+  const double lg = double(31 - __clz(p.L));
+  const double e = u * ((lg * p.kmax[m] * p.anorm + p.beta[m]) * sqrt(xx) / bnorm + 1.0);
+  return fmax(kPcgSlack * p.tol, p.floor_scale * e);
+}
 
 // ------------------------------------------------------------- phases
 // Wait until *addr >= target (thread 0 polls with agent-scope acquire,
@@ -954,7 +968,7 @@ __device__ __forceinline__ void phase_r0(const Prob& p, int m, int rank, const L
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
     tileC_load_ifft<double>(pl, tile, p.T, L.bd);
-    double acc[1] = {0.0};
+    double acc[2] = {0.0, 0.0};
     for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
       int i0, sl;
       item(pl, t, idx, i0, sl);
@@ -964,6 +978,7 @@ __device__ __forceinline__ void phase_r0(const Prob& p, int m, int rank, const L
         y = mask2(cscale<double>(L.bd[sl], inv), i0, p.n);
         const double2 xx = ld2(x, off), kk = ld2(p.kap, off), b = ld2(p.vec[VB], off);
         r = mask2(make_double2(b.x - (bm * xx.x + kk.x * y.x), b.y - (bm * xx.y + kk.y * y.y)), i0, p.n);
+        acc[1] += xx.x * xx.x + xx.y * xx.y;
       }
       st2(Aum, off, y);
       st2(p.vec[VR], off, r);
@@ -971,8 +986,8 @@ __device__ __forceinline__ void phase_r0(const Prob& p, int m, int rank, const L
       acc[0] += r.x * r.x + r.y * r.y;
       lbuf<RP>(L)[sl] = tocx<RP>(pc_in(p, off, r));
     }
-    const int sl_rr[1] = {SL_RR};
-    write_partials<1>(p, tile, sl_rr, acc);
+    const int sl_rr[2] = {SL_RR, SL_XX};
+    write_partials<2>(p, tile, sl_rr, acc);
     tileA_fft_store<RP>(pl, tile, lbuf<RP>(L), pT<RP>(p));
   }
 }
@@ -1670,12 +1685,20 @@ __device__ __forceinline__ int level_pcg(const Prob& p, int m, int rank, Ctl& ct
       phase_r0<double>(p, m, rank, L);
       BARRIER();
       ++mv;
-      reduce_slots<1>(p, sl1, red1);
-      const double rt = red1[0];
+      double red2x[2];
+      const int slx[2] = {SL_RR, SL_XX};
+      reduce_slots<2>(p, slx, red2x);
+      const double rt = red2x[0];
       if (bad(rt)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
-      if (sqrt(rt) <= kPcgSlack * tol * bnorm || ++checks >= kPcgChecks || !(rt < 0.25 * rr_true_prev)) {
+      if (sqrt(rt) <= kPcgSlack * tol * bnorm) {
         write_info(p, rank, m, it, mv, sqrt(rt) / bnorm, FIDS_OK);
         return FIDS_OK;
+      }
+      if (++checks >= kPcgChecks || !(rt < 0.25 * rr_true_prev)) {
+        // stalled: accepted at the FP64 floor only within its rounding level
+        const bool ok = sqrt(rt) <= floor_bound(p, m, red2x[1], bnorm) * bnorm;
+        write_info(p, rank, m, it, mv, sqrt(rt) / bnorm, ok ? FIDS_OK : FIDS_ENOCONV);
+        return ok ? FIDS_OK : FIDS_ENOCONV;
       }
       rr_true_prev = rt;
       rr = rt;
@@ -1949,6 +1972,7 @@ __device__ __forceinline__ void phase_pc_col64(const Prob& p, int rank, const Ld
 // Counters a level carries from one restart cycle to the next.
 struct Cyc {
   double rr;          // ||r||^2 of the true residual in VR
+  double xx;          // ||x||^2 of the iterate it belongs to (after a cycle)
   int it, mv, floor_hits, it64;
   bool est_conv;
 };
@@ -1964,7 +1988,7 @@ constexpr int kFallback = 1;   // internal: continue the level with the FP64 pre
 template <typename RP>
 __device__ __forceinline__ int fgmres_cycles(const Prob& p, int m, int rank, Ctl& ctl, const Lds& L, const Hess& H,
                                              double bnorm, Cyc& c) {
-  double rr = c.rr;
+  double rr = c.rr, xx = c.xx;
   int it = c.it, mv = c.mv, floor_hits = c.floor_hits, it64 = c.it64;
   bool est_conv = c.est_conv;
   const RP* Q = pQ<RP>(p, m);
@@ -1974,10 +1998,12 @@ __device__ __forceinline__ int fgmres_cycles(const Prob& p, int m, int rank, Ctl
   for (;;) {                                   // restart cycles
     const double beta0 = sqrt(rr);
     if (est_conv && beta0 > tol * bnorm && ++floor_hits >= 2) {
-      // the true FP64 residual has reached its attainable floor: accept and
-      // report the true relative residual
-      write_info(p, rank, m, it, mv, beta0 / bnorm, FIDS_OK, it64);
-      return FIDS_OK;
+      // the Arnoldi estimate met the tolerance twice but the true FP64
+      // residual did not: accepted at that floor only within its rounding
+      // level, with the true relative residual reported
+      const int st = beta0 <= floor_bound(p, m, xx, bnorm) * bnorm ? FIDS_OK : FIDS_ENOCONV;
+      write_info(p, rank, m, it, mv, beta0 / bnorm, st, it64);
+      return st;
     }
     if (beta0 <= tol * bnorm) {
       write_info(p, rank, m, it, mv, bnorm > 0 ? beta0 / bnorm : 0.0, FIDS_OK, it64);
@@ -1986,7 +2012,7 @@ __device__ __forceinline__ int fgmres_cycles(const Prob& p, int m, int rank, Ctl
     if (it >= p.maxit) { write_info(p, rank, m, it, mv, beta0 / bnorm, FIDS_ENOCONV, it64); return FIDS_ENOCONV; }
     if constexpr (sizeof(RP) == 4) {
       if (p.qhat != nullptr && p.zd != nullptr && it >= J) {
-        c.rr = rr; c.it = it; c.mv = mv; c.floor_hits = floor_hits; c.it64 = 0; c.est_conv = est_conv;
+        c.rr = rr; c.xx = xx; c.it = it; c.mv = mv; c.floor_hits = floor_hits; c.it64 = 0; c.est_conv = est_conv;
         return kFallback;
       }
     }
@@ -2066,10 +2092,12 @@ __device__ __forceinline__ int fgmres_cycles(const Prob& p, int m, int rank, Ctl
     BARRIER();
     ++mv;
     {
-      const int sl[1] = {SL_RR};
-      reduce_slots<1>(p, sl, red1);
+      double red2[2];
+      const int sl[2] = {SL_RR, SL_XX};
+      reduce_slots<2>(p, sl, red2);
+      rr = red2[0];
+      xx = red2[1];
     }
-    rr = red1[0];
     if (bad(rr)) { write_info(p, rank, m, it, mv, NAN, FIDS_ENUMERIC, it64); return FIDS_ENUMERIC; }
   }
 }
@@ -2085,7 +2113,7 @@ __device__ __forceinline__ int level_fgmres(const Prob& p, int m, int rank, Ctl&
     if (st != FIDS_OK) return st;
   }
   if (bad(bb) || bad(rr)) { write_info(p, rank, m, 0, 0, NAN, FIDS_ENUMERIC); return FIDS_ENUMERIC; }
-  Cyc c{rr, 0, (p.x0_mode != 0) ? 1 : 0, 0, 0, false};
+  Cyc c{rr, 0.0, 0, (p.x0_mode != 0) ? 1 : 0, 0, 0, false};
   const int st = fgmres_cycles<RP>(p, m, rank, ctl, L, H, sqrt(bb), c);
   if constexpr (sizeof(RP) == 4) {
     if (st == kFallback) {
@@ -2133,7 +2161,7 @@ __device__ __forceinline__ void run_member(const Prob& p, int rank, int m_begin,
   const int tab_c = (3 * p.nexp + 1) / 2;
   const int small_c = kSmallDoubles / 2;
   const int tile_pts = max(2 * p.pl.CT * p.pl.N1, 4 * p.pl.RU * p.pl.N2);
-  const int nlo = p.pl.twmask + 1, nhi = p.L >> p.pl.twshift;
+  const int nlo = p.pl.twmask + 1;
   const int ntw = p.pl.twn;               // twiddles copied to LDS (set with twres)
   const bool mixed = p.precision == FIDS_MIXED;
   Lds L;
@@ -2300,13 +2328,27 @@ __global__ void __launch_bounds__(kThreads) k_from_natural(const Prob* pp, const
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_kbar(const double* kappa, int n, int td, double* kbar) {
-  const int m = blockIdx.x + 1;
+__global__ void __launch_bounds__(kThreads) k_kbar(const double* kappa, int n, int m0, int td, double* kbar,
+                                                   double* kmax) {
+  __shared__ double red[kThreads / 64];
+  const int m = m0 + int(blockIdx.x);
   const double* row = kappa + (td ? size_t(m - 1) * n : 0);
   double acc[1] = {0.0};
-  for (int i = threadIdx.x; i < n; i += kThreads) acc[0] += row[i];
+  double mx = -INFINITY;
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    acc[0] += row[i];
+    mx = fmax(mx, row[i]);
+  }
   block_sum<1>(acc);
-  if (threadIdx.x == 0) kbar[m] = acc[0] / double(n);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / 64; ++w) mx = fmax(mx, red[w]);
+    kbar[m] = acc[0] / double(n);
+    kmax[m] = mx;
+  }
 }
 
 // Symbols, step 1: complex column pass of a_k = chirp_k / (b_m' + kbar_m lam_k).
@@ -2436,8 +2478,9 @@ hipError_t launch_from_natural(const Prob& h, const Prob* d, const double* src, 
   return hipGetLastError();
 }
 
-hipError_t launch_kbar(const double* kappa, int n, int M, int td, double* kbar, hipStream_t s) {
-  hipLaunchKernelGGL(k_kbar, dim3(M), dim3(kThreads), 0, s, kappa, n, td, kbar);
+hipError_t launch_kbar(const double* kappa, int n, int m0, int cnt, int td, double* kbar, double* kmax,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_kbar, dim3(cnt), dim3(kThreads), 0, s, kappa, n, m0, td, kbar, kmax);
   return hipGetLastError();
 }
 

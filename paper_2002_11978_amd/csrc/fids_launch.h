@@ -13,8 +13,10 @@ size_t level_lds_bytes(const Prob& h);
 // Clears the state of one problem and sets u^0 = phi (tile-major).
 hipError_t launch_init_state(const Prob& h, const Prob* d, hipStream_t s);
 
-// Mean of kappa^m for m = 1..M (or the single row) into kbar[1..M].
-hipError_t launch_kbar(const double* kappa, int n, int M, int td, double* kbar, hipStream_t s);
+// Mean and largest entry of kappa^m for m = m0..m0+cnt-1 (rows m-1 of a
+// [M][n] kappa, or its single row) into kbar[m] and kmax[m].
+hipError_t launch_kbar(const double* kappa, int n, int m0, int cnt, int td, double* kbar, double* kmax,
+                       hipStream_t s);
 
 // Per-level preconditioner symbols for levels [m0, m0 + cnt).
 hipError_t launch_symbols(const SymJob& job, const SymJob* d, int m0, int cnt, hipStream_t s);

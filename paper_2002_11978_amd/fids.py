@@ -22,6 +22,7 @@ FIDS_BICGSTAB, FIDS_FGMRES, FIDS_PCG = 0, 1, 2
 FIDS_FP64, FIDS_MIXED = 0, 1
 FIDS_STRANG, FIDS_NONE, FIDS_STRANG_K = 0, 1, 2
 FIDS_HISTORY_SOE, FIDS_HISTORY_DIRECT = 0, 1
+FIDS_LEVEL_ABOVE_TOL = 1
 
 
 class Params(ctypes.Structure):
@@ -39,7 +40,7 @@ class Params(ctypes.Structure):
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("iters", ctypes.c_int32), ("matvecs", ctypes.c_int32),
-                ("relres", ctypes.c_double), ("pc_fp64_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("relres", ctypes.c_double), ("pc_fp64_iters", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class FidsError(RuntimeError):
@@ -65,6 +66,7 @@ _SIGS = {
                                          ctypes.POINTER(_P)]),
     "fids_step": (ctypes.c_int, [_P, _P, ctypes.POINTER(StepInfo)]),
     "fids_solve_all": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(StepInfo)]),
+    "fids_solve_levels": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.POINTER(StepInfo)]),
     "fids_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "fids_adjoint_report": (ctypes.c_int, [_P, ctypes.POINTER(StepInfo)]),
     "fids_reset": (ctypes.c_int, [_P]),
@@ -221,6 +223,11 @@ class LevelReport:
     matvecs: int
     relres: float
     pc_fp64_iters: int = 0
+    flags: int = 0
+
+    @classmethod
+    def of(cls, i):
+        return cls(i.m, i.iters, i.matvecs, i.relres, i.pc_fp64_iters, i.flags)
 
 
 class Problem:
@@ -260,7 +267,20 @@ class Problem:
         u = self.torch.empty(self.n, dtype=self.torch.float64, device=self.device)
         info = StepInfo()
         _check(lib().fids_step(self.h, _ptr(u), ctypes.byref(info)), "fids_step")
-        return u, LevelReport(info.m, info.iters, info.matvecs, info.relres, info.pc_fp64_iters)
+        return u, LevelReport.of(info)
+
+    def solve_levels(self, count, want_u=True):
+        """Advance `count` levels in one launch; returns (u at the new level, reports)."""
+        u = self.torch.empty(self.n, dtype=self.torch.float64, device=self.device) if want_u else None
+        infos = (StepInfo * count)()
+        st = lib().fids_solve_levels(self.h, count, _ptr(u), infos)
+        self.last_reports = [LevelReport.of(i) for i in infos if i.m > 0]
+        _check(st, "fids_solve_levels")
+        return u, self.last_reports
+
+    def solve_levels_raw(self, count, u=None, infos=None):
+        """fids_solve_levels with caller-provided outputs (no allocation); returns the status."""
+        return lib().fids_solve_levels(self.h, count, _ptr(u), infos)
 
     def solve_all(self, return_all=False, want_uT=True):
         torch = self.torch
@@ -268,7 +288,7 @@ class Problem:
         uall = torch.empty((self.M + 1, self.n), dtype=torch.float64, device=self.device) if return_all else None
         infos = (StepInfo * self.M)()
         st = lib().fids_solve_all(self.h, _ptr(uT), _ptr(uall), infos)
-        self.last_reports = [LevelReport(i.m, i.iters, i.matvecs, i.relres, i.pc_fp64_iters) for i in infos]
+        self.last_reports = [LevelReport.of(i) for i in infos]
         _check(st, "fids_solve_all")
         return uT, uall, self.last_reports
 
@@ -299,7 +319,7 @@ class Problem:
     def adjoint_reports(self):
         infos = (StepInfo * self.M)()
         _check(lib().fids_adjoint_report(self.h, infos), "fids_adjoint_report")
-        return [LevelReport(i.m, i.iters, i.matvecs, i.relres, i.pc_fp64_iters) for i in infos]
+        return [LevelReport.of(i) for i in infos]
 
     def reset(self):
         _check(lib().fids_reset(self.h), "fids_reset")
@@ -356,7 +376,7 @@ class Batch:
         self.h = h
 
     def _reports(self, infos):
-        return [[LevelReport(i.m, i.iters, i.matvecs, i.relres, i.pc_fp64_iters) for i in infos[p * self.M:(p + 1) * self.M]]
+        return [[LevelReport.of(i) for i in infos[p * self.M:(p + 1) * self.M]]
                 for p in range(self.count)]
 
     def solve_all(self, want_uT=True):
@@ -375,7 +395,7 @@ class Batch:
     def step(self):
         infos = (StepInfo * self.count)()
         _check(lib().fids_batch_step(self.h, infos), "fids_batch_step")
-        return [LevelReport(i.m, i.iters, i.matvecs, i.relres, i.pc_fp64_iters) for i in infos]
+        return [LevelReport.of(i) for i in infos]
 
     def status(self):
         st = (ctypes.c_int32 * self.count)()
