@@ -228,6 +228,25 @@ int fids_solve_levels(fids_problem* h, int64_t count, double* u_out_d, fids_step
  * the levels advanced by this call (index m-1). */
 int fids_solve_all(fids_problem* h, double* uT_d, double* u_all_d, fids_step_info* per_step);
 
+/* Allocation-free solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): fids_init_problem + fids_solve_all + fids_destroy in one call,
+ * with the workspace taken from a fixed 64 MiB device array inside the
+ * library (each device holds its own copy until the process ends) instead of
+ * a caller's buffer.  The call makes no hipMalloc / hipFree; host memory for
+ * the set-up tables is allocated and released as in fids_init_problem.
+ * Arguments as in fids_init_problem and fids_solve_all: uT_d (may be NULL)
+ * receives u^M, per_step (may be NULL) is a host array of M reports.  The
+ * problem's workspace (with a 4 MiB batch for the per-level symbols) must fit
+ * the array: problems up to about n = 4095 with M = 512 do; larger ones get
+ * FIDS_EINVAL with the sizes in fids_last_error().  Calls on one device share
+ * the array: this library serialises them within a process (each call clears
+ * what it uses and synchronises hip_stream before returning), and calls that
+ * overlap on one device from separate processes are not possible because
+ * each process has its own array. */
+int fids_solve_static(const fids_params* p, const double* kappa_d, const double* f_d, const double* phi_d,
+                      double* uT_d, fids_step_info* per_step, void* hip_stream);
+
 /* Exact discrete adjoint of the FIDS steps (eq. 3.16gu with the SOE history
  * recurrence of Lemma 2.2 / eq. 2.9), for a loss J(u^M): given dJ/du^M
  * (dJ_duT_d, [n]) it returns dJ/dkappa (shape of kappa_d: [M][n] or [n]),

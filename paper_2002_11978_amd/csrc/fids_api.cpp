@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -112,7 +113,11 @@ struct Shapes {
   PlanShape pr, pc, ps;   // level plan, Bluestein (complex L) plan, symbol (real) plan
 };
 
-Layout make_layout(const fids_params& p, const Shapes& sh) {
+// Device memory the per-level symbol construction may use for its batches of
+// levels (the caller's workspace; the allocation-free entry point uses less).
+constexpr size_t kSymBudget = size_t(64) << 20;
+
+Layout make_layout(const fids_params& p, const Shapes& sh, size_t sym_budget = kSymBudget) {
   Layout lo{};
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + std::max<size_t>(bytes, 1)); return o; };
@@ -155,9 +160,9 @@ Layout make_layout(const fids_params& p, const Shapes& sh) {
   // FP64 symbols always (the mixed form falls back to them), FP32 copies for the mixed form
   lo.qhat = take((M + 1) * (Nc + 1) * 8);
   lo.qhatf = mixed ? take((M + 1) * (Nc + 1) * 4) : 0;
-  // symbol scratch: about 64 MiB per chunk
+  // symbol scratch: levels built together, about sym_budget bytes
   const size_t per = L * 16 + n * 8 + Nc * 16;
-  lo.chunk = int(std::max<size_t>(1, std::min<size_t>(M, (size_t(64) << 20) / per)));
+  lo.chunk = int(std::max<size_t>(1, std::min<size_t>(M, sym_budget / per)));
   lo.Tb = take(size_t(lo.chunk) * L * 16);
   lo.q = take(size_t(lo.chunk) * n * 8);
   lo.Tq = take(size_t(lo.chunk) * Nc * 16);
@@ -454,7 +459,8 @@ void batch_params(fids_params& p, int group = 1) {
 // workgroup (ng = 1, no helpers, no snapshots); the batch sets the LDS limit
 // and synchronises once for all of its members.
 int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, const double* phi_d,
-              void* ws_d, size_t ws_bytes, void* hip_stream, int batch_group, fids_problem** out) {
+              void* ws_d, size_t ws_bytes, void* hip_stream, int batch_group, fids_problem** out,
+              size_t sym_budget = kSymBudget) {
   const bool batch = batch_group > 0;
   fids_params pb = *pin;
   if (batch) batch_params(pb, batch_group);
@@ -471,7 +477,7 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
     return FIDS_EINVAL;
   }
   h->sh.nexp = h->tab.nexp;
-  h->lo = make_layout(*p, h->sh);
+  h->lo = make_layout(*p, h->sh, sym_budget);
   if (ws_bytes < h->lo.total) { delete h; return FIDS_EINVAL; }
   h->stream = static_cast<hipStream_t>(hip_stream);
   h->ws = static_cast<char*>(ws_d);
@@ -829,9 +835,75 @@ int batch_finish(fids_batch* b, int m0, int m1) {
   return st;
 }
 
+// ------------------------------------------------ allocation-free entry point
+// Workspace of fids_solve_static: a fixed device array in the library's code
+// object, so the call allocates no device memory.  Each device the library
+// runs on holds its own copy (kScratchBytes) from module load to process end.
+// In host code `scratch` only names the symbol: its device address comes
+// from hipGetSymbolAddress, once per device with that device current.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr size_t kScratchSymBudget = size_t(4) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch` (looked up on the
+// first call on that device; the caller holds g_scratch_mu[dev]).
+int scratch_address(int dev, void** out) {
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || reinterpret_cast<uintptr_t>(ptr) % kAlign) return FIDS_EDEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FIDS_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int fids_solve_static(const fids_params* p, const double* kappa_d, const double* f_d, const double* phi_d,
+                      double* uT_d, fids_step_info* per_step, void* hip_stream) {
+  if (!p || !kappa_d || !f_d || !phi_d) return FIDS_EINVAL;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return FIDS_EINVAL;
+  // one call at a time per device in this process: the array is shared
+  std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+  void* ws = nullptr;
+  int st = scratch_address(dev, &ws);
+  if (st != FIDS_OK) return st;
+  {
+    Shapes sh;
+    if (shapes_of(*p, sh, nullptr) != FIDS_OK) return FIDS_EINVAL;
+    fids_params q = *p;
+    if (q.history == FIDS_HISTORY_DIRECT) q.store_states = 1;
+    const size_t need = make_layout(q, sh, kScratchSymBudget).total;
+    if (need > kScratchBytes) {
+      std::snprintf(g_last_error, sizeof(g_last_error),
+                    "fids_solve_static: the problem needs %zu bytes of device memory, the static array holds %zu",
+                    need, kScratchBytes);
+      return FIDS_EINVAL;
+    }
+  }
+  fids_problem* h = nullptr;
+  // init clears the part of the array the problem uses (the last call's
+  // contents are still there)
+  st = init_impl(p, kappa_d, f_d, phi_d, ws, kScratchBytes, hip_stream, 0, &h, kScratchSymBudget);
+  if (st != FIDS_OK) return st;
+  st = run_levels(h, h->sh.M, per_step);
+  if (st == FIDS_OK && uT_d) {
+    if (hip_bad(fids::launch_to_natural(h->hp, h->dp, h->hp.u[h->sh.M % fids::kRing], uT_d, h->stream), __LINE__))
+      st = FIDS_EDEVICE;
+  }
+  if (hip_bad(hipStreamSynchronize(h->stream), __LINE__) && st == FIDS_OK) st = FIDS_EDEVICE;
+  delete h;
+  return st;
+}
 
 int fids_params_default(fids_params* p) {
   if (!p) return FIDS_EINVAL;

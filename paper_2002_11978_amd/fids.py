@@ -67,6 +67,7 @@ _SIGS = {
     "fids_step": (ctypes.c_int, [_P, _P, ctypes.POINTER(StepInfo)]),
     "fids_solve_all": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(StepInfo)]),
     "fids_solve_levels": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.POINTER(StepInfo)]),
+    "fids_solve_static": (ctypes.c_int, [ctypes.POINTER(Params), _P, _P, _P, _P, ctypes.POINTER(StepInfo), _P]),
     "fids_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "fids_adjoint_report": (ctypes.c_int, [_P, ctypes.POINTER(StepInfo)]),
     "fids_reset": (ctypes.c_int, [_P]),
@@ -214,6 +215,21 @@ def level_coefficients(gamma, T, M, r):
 # ------------------------------------------------------------------ device problems
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def solve_static(params: Params, kappa, f, phi, stream=None):
+    """fids_solve_static: one allocation-free solve to level M (the library's
+    fixed device array as workspace); returns (u^M, reports)."""
+    import torch
+    for name, t in (("kappa", kappa), ("f", f), ("phi", phi)):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float64 device tensor")
+    s = stream if stream is not None else torch.cuda.current_stream(kappa.device)
+    uT = torch.empty(int(params.n), dtype=torch.float64, device=kappa.device)
+    infos = (StepInfo * int(params.M))()
+    _check(lib().fids_solve_static(ctypes.byref(params), _ptr(kappa), _ptr(f), _ptr(phi), _ptr(uT), infos,
+                                   ctypes.c_void_p(s.cuda_stream)), "fids_solve_static")
+    return uT, [LevelReport.of(i) for i in infos]
 
 
 @dataclass
