@@ -20,6 +20,6 @@ Lemma 4.1 and brute force; see the docstrings for the passage each follows.
 """
 from .fids_oracle import (  # noqa: F401
     c1_alpha, graded_mesh, step_sizes, l1_weights, ifl_column, ifl_matrix,
-    strang_column, dids_solve, dids_adjoint, errors, loss_and_grad_fd,
+    strang_column, dids_solve, dids_adjoint, errors,
     soe_relative_error, fids_history_weights,
 )

@@ -197,11 +197,6 @@ def errors(U: np.ndarray, exact: np.ndarray, l: float = 1.0):
     return float(np.max(np.abs(E))), float(np.max(np.sqrt(h * np.sum(E * E, axis=1))))
 
 
-def loss_and_grad_fd(solve, theta, direction, eps):
-    """Central difference (J(theta + eps d) - J(theta - eps d)) / (2 eps)."""
-    return (solve(theta + eps * direction) - solve(theta - eps * direction)) / (2 * eps)
-
-
 # ---------------------------------------------------------------- SOE checks
 def soe_relative_error(s, w, gamma, delta, T, npts=4000):
     """max over a log grid of [delta, T] of |t^gamma sum_j w_j e^{-s_j t} - 1|
