@@ -316,6 +316,13 @@ int fids_batch_step(fids_batch* b, fids_step_info* info);
  * array [count][M]. */
 int fids_batch_solve_all(fids_batch* b, double* const* uT_d, fids_step_info* info);
 
+/* Advance every problem by `count` levels (1 <= count <= M - level) in one
+ * launch (the batch's per-level graph is not used); u_d (may be NULL) is a
+ * host array with one device pointer per member (NULL entries skipped) that
+ * receive each member's state at the new level; info (may be NULL) is a host
+ * array [members][M] of the reports of every level run so far. */
+int fids_batch_solve_levels(fids_batch* b, int64_t count, double* const* u_d, fids_step_info* info);
+
 /* Per-member status after the last batch call: status[i] (FIDS_OK or the
  * member's failure; a failed member stops while the others go on) and, if
  * last_level is not NULL, the last level member i completed.  Host arrays of

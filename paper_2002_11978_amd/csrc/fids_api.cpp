@@ -1239,6 +1239,29 @@ int fids_batch_solve_all(fids_batch* b, double* const* uT_d, fids_step_info* inf
   return FIDS_OK;
 }
 
+int fids_batch_solve_levels(fids_batch* b, int64_t count, double* const* u_d, fids_step_info* info) {
+  if (!b) return FIDS_EINVAL;
+  if (b->level >= b->M || b->poisoned) return FIDS_ESTATE;
+  if (count < 1 || count > b->M - b->level) return FIDS_EINVAL;
+  int st = batch_symbols(b);
+  if (st != FIDS_OK) return st;
+  const int m0 = int(b->level + 1), m1 = int(b->level + count);
+  HIPCHK(batch_launch(b, m0, m1, b->stream));
+  st = batch_finish(b, m0, m1);
+  if (info) HIPCHK(hipMemcpy(info, b->dinfo, size_t(b->count) * size_t(b->M) * sizeof(fids_step_info),
+                             hipMemcpyDeviceToHost));
+  if (st != FIDS_OK) return st;
+  if (u_d) {
+    for (int32_t i = 0; i < b->count; ++i) {
+      if (!u_d[i]) continue;
+      const fids_problem* h = b->members[size_t(i)];
+      HIPCHK(fids::launch_to_natural(h->hp, h->dp, h->hp.u[m1 % fids::kRing], u_d[i], b->stream));
+    }
+    HIPCHK(hipStreamSynchronize(b->stream));
+  }
+  return FIDS_OK;
+}
+
 int fids_batch_status(const fids_batch* b, int32_t* status, int64_t* last_level) {
   if (!b || !status) return FIDS_EINVAL;
   std::vector<int> w(size_t(b->count) * 4);

@@ -82,6 +82,7 @@ _SIGS = {
                                        ctypes.POINTER(_P)]),
     "fids_batch_step": (ctypes.c_int, [_P, ctypes.POINTER(StepInfo)]),
     "fids_batch_solve_all": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(StepInfo)]),
+    "fids_batch_solve_levels": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(_P), ctypes.POINTER(StepInfo)]),
     "fids_batch_status": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
     "fids_batch_groups": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "fids_batch_tune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -407,6 +408,17 @@ class Batch:
 
     def solve_all_raw(self, uT_ptrs=None, infos=None):
         return lib().fids_batch_solve_all(self.h, uT_ptrs, infos)
+
+    def solve_levels(self, count, want_u=True):
+        """Advance every member `count` levels in one launch; returns (states, reports so far)."""
+        torch = self.torch
+        outs = [torch.empty(n, dtype=torch.float64, device=self.device) for n in self.ns] if want_u else None
+        ptrs = (_P * self.count)(*[t.data_ptr() for t in outs]) if want_u else None
+        infos = (StepInfo * (self.count * self.M))()
+        st = lib().fids_batch_solve_levels(self.h, count, ptrs, infos)
+        self.last_reports = self._reports(infos)
+        _check(st, "fids_batch_solve_levels")
+        return outs, self.last_reports
 
     def step(self):
         infos = (StepInfo * self.count)()

@@ -227,10 +227,13 @@ def test_finite_differences_reduced(kw):
     _fd_check(pb, ustar, 16, 8, 1e-6, checkpoint_every=8, **kw)
 
 
-def test_finite_differences_adjoint_workload():
+@pytest.mark.parametrize("kw", [pytest.param(dict(solver=1, x0_mode=1), id="fgmres-x0linear"),
+                                pytest.param(dict(solver=2, x0_mode=3), id="pcg-x0cubic")])
+def test_finite_differences_adjoint_workload(kw):
     """n = 16383, M = 1024, alpha 1.6, gamma 0.5, r 3, time-independent kappa
     (seed 5); target u* = u^M of a second kappa (seed 6); f seed 7; snapshots
-    every 32 levels; 16 unit directions (seed 8) over (kappa, f, phi)."""
+    every 32 levels; 16 unit directions (seed 8) over (kappa, f, phi); the
+    FGMRES form and the benchmark's conjugate-gradient form."""
     import torch
     pb = W.seeded(1.6, 0.5, 16383, 1024, r=3.0, kappa_seed=5, f_seed=7, time_dependent=False)
     tgt = W.seeded(1.6, 0.5, 16383, 1024, r=3.0, kappa_seed=6, f_seed=7, time_dependent=False)
@@ -240,7 +243,7 @@ def test_finite_differences_adjoint_workload():
     ustar = ustar.cpu().numpy()
     prob.close()
     torch.cuda.synchronize()
-    _fd_check(pb, ustar, 16, 8, 1e-6, checkpoint_every=32, solver=1, x0_mode=1)
+    _fd_check(pb, ustar, 16, 8, 1e-6, checkpoint_every=32, **kw)
 
 
 def test_autograd_function_matches_adjoint():

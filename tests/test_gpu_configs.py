@@ -1,0 +1,128 @@
+"""GPU parity at the benchmark workloads' own parameters, against answers the
+oracle wrote once (tests/golden/make_config_references.py; direct scheme,
+dense LU per level, full L1 history, and its exact discrete adjoint).
+
+  * plain-method workload: n = 4095, M = 512, (alpha, gamma) = (1.2, 0.3) and
+    (1.8, 0.7), r = (2-gamma)/gamma, seeded kappa(x,t) and f(x,t) (seeds 1, 2):
+    u^256 and u^512 of the paper's solver (BiCGSTAB, zero initial guess),
+    conjugate gradients and flexible GMRES, all FP64;
+  * the 256-problem batch (n log-uniform in [511, 16383], alpha ~ U(1.1, 1.9),
+    gamma ~ U(0.2, 0.8), M = 256) in its three benchmark forms: u^128 and
+    u^256 of 12 members with n <= 4095 spanning gamma, alpha and n;
+  * the adjoint workload (alpha 1.6, gamma 0.5, r 3, time-independent kappa)
+    at n = 1023 with its full M = 1024 and snapshots every 32 levels:
+    dJ/dkappa, dJ/dphi and rows of dJ/df of J = ||u^M - u*||^2.
+
+Gates: relative max-norm error <= 1e-8 for FP64 paths and <= 1e-7 for the
+FP32-preconditioned form (the method differs from the oracle's direct scheme
+by the SOE tolerance 1e-10, Theorem 3.4, and by the Krylov tolerance).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2002_11978_amd import fids
+from paper_2002_11978_amd import workloads as W
+
+from gpu_util import rel_maxnorm, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-8
+TOL_MIXED = 1e-7
+
+
+def _load(name):
+    return np.load(os.path.join(GOLDEN, name), allow_pickle=False)
+
+
+@pytest.mark.parametrize("kw", [
+    pytest.param(dict(solver=0, x0_mode=0), id="bicgstab-x0zero"),
+    pytest.param(dict(solver=2, x0_mode=3), id="pcg-x0cubic"),
+    pytest.param(dict(solver=1, x0_mode=3), id="fgmres-x0cubic"),
+])
+@pytest.mark.parametrize("alpha,gamma", [(1.2, 0.3), (1.8, 0.7)])
+def test_plain_method_workload(alpha, gamma, kw):
+    ref = _load("c1_n4095_M512.npz")
+    pb = W.seeded(alpha, gamma, 4095, 512, kappa_seed=1, f_seed=2)
+    params = fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=pb.M, r=pb.r, soe_tol=1e-10,
+                                 krylov_tol=1e-10, krylov_maxit=1000, kappa_time_dependent=1, **kw)
+    say(f"[configs] plain-method workload alpha={alpha} gamma={gamma} r={pb.r:.4f} {kw}")
+    prob = fids.Problem(params, to_dev(pb.kappa), to_dev(pb.f), to_dev(pb.phi))
+    errs = []
+    for m_to, count in ((256, 256), (512, 256)):
+        u, reps = prob.solve_levels(count)
+        errs.append(rel_maxnorm(u.cpu().numpy(), ref[f"a{alpha}_g{gamma}_u{m_to}"]))
+    prob.close()
+    say(f"  rel err u^256 {errs[0]:.3e}, u^512 {errs[1]:.3e}")
+    assert max(errs) <= TOL
+
+
+C3_MEMBERS = [118, 66, 44, 70, 50, 121, 104, 197, 133, 22, 18, 149]
+
+
+@pytest.fixture(scope="module")
+def batch_arrays():
+    pbs = [W.batch_member(p, M=256) for p in range(256)]
+    arrs = [[to_dev(getattr(pb, a)) for pb in pbs] for a in ("kappa", "f", "phi")]
+    return pbs, arrs
+
+
+@pytest.mark.parametrize("name,cfg", [
+    pytest.param("fp64", dict(solver=1, precision=0, x0_mode=3, precond=2), id="fgmres-fp64"),
+    pytest.param("mixed", dict(solver=1, precision=1, x0_mode=3, precond=2), id="fgmres-mixed"),
+    pytest.param("pcg", dict(solver=2, precision=0, x0_mode=3, precond=2), id="pcg-fp64"),
+])
+def test_batch_members(batch_arrays, name, cfg):
+    ref = _load("c3_members_M256.npz")
+    pbs, arrs = batch_arrays
+    params = [fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=256, r=pb.r, soe_tol=1e-10,
+                                  krylov_tol=1e-10, krylov_maxit=500, **cfg) for pb in pbs]
+    say(f"[configs] 256-member batch {name}")
+    b = fids.Batch(params, *arrs)
+    b.tune(levels=4)
+    out = {}
+    for m_to in (128, 256):
+        us, reps = b.solve_levels(128)
+        for p in C3_MEMBERS:
+            out[(p, m_to)] = us[p].cpu().numpy()
+    st, last = b.status()
+    b.close()
+    assert all(s == 0 for s in st) and all(x == 256 for x in last)
+    gate = TOL_MIXED if cfg["precision"] == 1 else TOL
+    worst = 0.0
+    for p in C3_MEMBERS:
+        e = max(rel_maxnorm(out[(p, m)], ref[f"m{p}_u{m}"]) for m in (128, 256))
+        fb = sum(r.pc_fp64_iters > 0 for r in reps[p])
+        say(f"  member {p}: n={pbs[p].n} alpha={pbs[p].alpha:.3f} gamma={pbs[p].gamma:.3f} "
+            f"rel err {e:.3e}, levels with the FP64 preconditioner {fb}")
+        worst = max(worst, e)
+    assert worst <= gate
+
+
+@pytest.mark.parametrize("kw", [
+    pytest.param(dict(solver=2, x0_mode=3), id="pcg-x0cubic"),
+    pytest.param(dict(solver=1, x0_mode=1), id="fgmres-x0linear"),
+])
+def test_adjoint_workload_gradient(kw):
+    ref = _load("c4_grad_n1023_M1024.npz")
+    pb = W.seeded(1.6, 0.5, 1023, 1024, r=3.0, kappa_seed=5, f_seed=7, time_dependent=False)
+    params = fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=pb.M, r=pb.r, soe_tol=1e-10,
+                                 krylov_tol=1e-12, krylov_maxit=500, kappa_time_dependent=0,
+                                 checkpoint_every=32, **kw)
+    say(f"[configs] adjoint workload n={pb.n} M={pb.M} {kw}")
+    prob = fids.Problem(params, to_dev(pb.kappa), to_dev(pb.f), to_dev(pb.phi))
+    uT, _, _ = prob.solve_all()
+    ustar = to_dev(ref["ustar"])
+    J = float(((uT - ustar) ** 2).sum())
+    gk, gf, gphi = prob.adjoint((2.0 * (uT - ustar)).contiguous())
+    prob.close()
+    rows = [int(m) - 1 for m in ref["g_f_rows"]]
+    errs = dict(J=abs(J - float(ref["J"])) / abs(float(ref["J"])),
+                kappa=rel_maxnorm(gk.cpu().numpy(), ref["g_kappa"]),
+                phi=rel_maxnorm(gphi.cpu().numpy(), ref["g_phi"]),
+                f=rel_maxnorm(gf.cpu().numpy()[rows], ref["g_f"]))
+    say("  rel err " + ", ".join(f"{k} {v:.3e}" for k, v in errs.items()))
+    assert max(errs.values()) <= TOL
