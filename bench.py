@@ -212,11 +212,18 @@ def batch_leg(tol, count):
            "count": count, "M": M}
     for name, cfg in (("fp64", dict(solver=1, precision=0, x0_mode=3, precond=2)),
                       ("mixed", dict(solver=1, precision=1, x0_mode=3, precond=2)),
-                      ("pcg", dict(solver=2, precision=0, x0_mode=3, precond=2))):
+                      ("pcg", dict(solver=2, precision=0, x0_mode=3, precond=2)),
+                      ("pcg_graph", dict(solver=2, precision=0, x0_mode=3, precond=2))):
         params = [fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=M, r=pb.r, soe_tol=1e-10,
                                       krylov_tol=tol, krylov_maxit=500, **cfg) for pb in pbs]
         t0 = time.perf_counter()
-        b = fids.Batch(params, *arrs)
+        if name.endswith("_graph"):
+            # one captured HIP-graph launch per level, every member on one workgroup
+            os.environ["FIDS_BATCH_MODE"] = "graph"
+        try:
+            b = fids.Batch(params, *arrs)
+        finally:
+            os.environ.pop("FIDS_BATCH_MODE", None)
         t_init = time.perf_counter() - t0
         t0 = time.perf_counter()
         b.tune(levels=4)
@@ -249,6 +256,8 @@ def batch_leg(tol, count):
                                   "launch": f"all {M} levels of the {count} members"},
                      "tune_s": t_tune,
                      "avg_iters": float(its.mean()), "levels_with_fp64_pc": int((fb > 0).sum()),
+                     "launch_mode": ("one captured HIP-graph launch per level, one workgroup per member"
+                                     if name.endswith("_graph") else "one persistent launch for all levels"),
                      "form": ("pcg-symmetrised-fp64-x0cubic-strang" if cfg["solver"] == 2 else
                               f"fgmres(20)-{'fp64' if cfg['precision'] == 0 else 'fp64/fp32pc'}-x0cubic-"
                               "kappa-scaled-strang")}

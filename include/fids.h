@@ -48,9 +48,11 @@
  *   FIDS_SKEW        moves factors of two from the column FFT length to the row
  *                    FFT length (default 0)
  *   FIDS_HELPERS     SOE helper workgroups when soe_helpers = -1 (default 0)
- *   FIDS_BATCH_MODE  "graph": a batch whose members all run on one workgroup
- *                    advances by one captured HIP-graph launch per level instead
- *                    of one persistent launch for all levels
+ *   FIDS_BATCH_MODE  "graph": a batch places every member on one workgroup
+ *                    and advances by one captured HIP-graph launch per level
+ *                    (fids_batch_solve_all from level 0; the graph is captured
+ *                    once and replayed) instead of one persistent launch for
+ *                    all levels
  *   FIDS_FLOOR_SCALE factor (default 1) on the rounding level up to which a
  *                    stalled true residual is accepted (FIDS_LEVEL_ABOVE_TOL);
  *                    0 accepts only residuals within 4 krylov_tol (changes

@@ -1107,6 +1107,12 @@ int fids_batch_init(const fids_params* p, int32_t count, const double* const* ka
   size_t lds_bound = 0;
   Prob probe{};
   if (batch_costs(p, count, cost, kmax, &lds_bound, &probe) != FIDS_OK) return fail(FIDS_EINVAL);
+  // graph mode: one workgroup per member, so that every level is an ordinary
+  // launch a HIP graph can hold (a group of several workgroups needs a
+  // cooperative launch)
+  const char* mode = std::getenv("FIDS_BATCH_MODE");
+  const bool want_graph = mode && std::strcmp(mode, "graph") == 0;
+  if (want_graph) kmax.assign(size_t(count), 1);
   int resident = count;
   {
     int dev = 0, cus = 0, per_cu = 0;
@@ -1169,9 +1175,7 @@ int fids_batch_init(const fids_params* p, int32_t count, const double* const* ka
     return fail(FIDS_EDEVICE);
   }
   if (hip_bad(hipStreamSynchronize(b->stream), __LINE__)) return fail(FIDS_EDEVICE);
-  const char* mode = std::getenv("FIDS_BATCH_MODE");
-  // a HIP graph holds ordinary launches only: one-workgroup members
-  b->graph_mode = mode && std::strcmp(mode, "graph") == 0 && !b->cooperative;
+  b->graph_mode = want_graph && !b->cooperative;
   *out = b;
   return FIDS_OK;
 }

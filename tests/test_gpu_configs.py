@@ -102,6 +102,41 @@ def test_batch_members(batch_arrays, name, cfg):
     assert worst <= gate
 
 
+@pytest.mark.parametrize("name,cfg", [
+    pytest.param("pcg", dict(solver=2, precision=0, x0_mode=3, precond=2), id="pcg-fp64"),
+    pytest.param("mixed", dict(solver=1, precision=1, x0_mode=3, precond=2), id="fgmres-mixed"),
+])
+def test_batch_members_graph_mode(batch_arrays, name, cfg):
+    """The 256-member batch advanced by one captured HIP-graph launch per
+    level (every member on one workgroup): u^256 of the 12 members against
+    the oracle, and every replay of the captured graph equal to the first."""
+    ref = _load("c3_members_M256.npz")
+    pbs, arrs = batch_arrays
+    params = [fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=256, r=pb.r, soe_tol=1e-10,
+                                  krylov_tol=1e-10, krylov_maxit=500, **cfg) for pb in pbs]
+    say(f"[configs] 256-member batch {name}, graph mode")
+    os.environ["FIDS_BATCH_MODE"] = "graph"
+    try:
+        b = fids.Batch(params, *arrs)
+    finally:
+        del os.environ["FIDS_BATCH_MODE"]
+    assert b.groups() == [1] * len(pbs)
+    first = None
+    for rep in range(3):
+        b.reset()
+        us, _ = b.solve_all()
+        got = {p: us[p].cpu().numpy() for p in C3_MEMBERS}
+        if first is None:
+            first = got
+        else:
+            assert all(np.array_equal(first[p], got[p]) for p in C3_MEMBERS)
+    b.close()
+    gate = TOL_MIXED if cfg["precision"] == 1 else TOL
+    errs = {p: rel_maxnorm(first[p], ref[f"m{p}_u256"]) for p in C3_MEMBERS}
+    say("  rel err " + ", ".join(f"{p}: {e:.2e}" for p, e in errs.items()))
+    assert max(errs.values()) <= gate
+
+
 @pytest.mark.parametrize("kw", [
     pytest.param(dict(solver=2, x0_mode=3), id="pcg-x0cubic"),
     pytest.param(dict(solver=1, x0_mode=1), id="fgmres-x0linear"),
