@@ -83,8 +83,9 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--table11", action="store_true",
                     help="Table 11 rows (Example 2) on the GPU: fast/direct history, with/without preconditioner")
-    ap.add_argument("--profile-pass", action="store_true",
-                    help="one headline launch of the level kernel plus a 256 MiB device copy (for counters)")
+    ap.add_argument("--profile-pass", nargs="?", const="headline", choices=["headline", "batch"],
+                    help="a 256 MiB device copy, then one launch of the level kernel over all levels: the "
+                         "headline form (default) or the 256-problem batch in its PCG form (for counters)")
     return ap.parse_args()
 
 
@@ -240,6 +241,19 @@ def batch_leg(tol, count):
             if st != 0:
                 raise fids.FidsError(st, "fids_batch_solve_all")
             best = dt if best is None else min(best, dt)
+        # the level kernel alone (symbols built first), for the roofline
+        b.reset()
+        b.prepare()
+        torch.cuda.synchronize()
+        k0 = torch.cuda.Event(enable_timing=True)
+        k1 = torch.cuda.Event(enable_timing=True)
+        k0.record(b.stream)
+        st = b.solve_all_raw(None, infos)
+        k1.record(b.stream)
+        torch.cuda.synchronize()
+        if st != 0:
+            raise fids.FidsError(st, "fids_batch_solve_all")
+        kern_ms = k0.elapsed_time(k1)
         its = np.array([infos[i].iters for i in range(count * M)])
         mvs = np.array([infos[i].matvecs for i in range(count * M)])
         fb = np.array([infos[i].pc_fp64_iters for i in range(count * M)])
@@ -249,11 +263,13 @@ def batch_leg(tol, count):
             for m in range(M):
                 k = p_i * M + m
                 nbytes += level_bytes(None, pb.n, nexps[p_i], int(its[k]), int(mvs[k]), cfg=cfg)
-        gbs = nbytes / best / 1e9
+        gbs = nbytes / (kern_ms * 1e-3) / 1e9
         out[name] = {"problem_levels_per_s": count * M / best, "solve_ms": best * 1e3, "init_s": t_init,
                      "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                   "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": nbytes,
-                                  "launch": f"all {M} levels of the {count} members"},
+                                  "kernel_ms_per_launch": kern_ms, "kernel": "k_levels",
+                                  "launch": f"all {M} levels of the {count} members, symbols prepared",
+                                  "traffic": None},
                      "tune_s": t_tune,
                      "avg_iters": float(its.mean()), "levels_with_fp64_pc": int((fb > 0).sum()),
                      "launch_mode": ("one captured HIP-graph launch per level, one workgroup per member"
@@ -261,8 +277,15 @@ def batch_leg(tol, count):
                      "form": ("pcg-symmetrised-fp64-x0cubic-strang" if cfg["solver"] == 2 else
                               f"fgmres(20)-{'fp64' if cfg['precision'] == 0 else 'fp64/fp32pc'}-x0cubic-"
                               "kappa-scaled-strang")}
+        tr = (measured_traffic(None, M, BATCH_TRAFFIC_FILE, "batch pcg-symmetrised-fp64-x0cubic", count)
+              if name == "pcg" else None)
+        if tr is not None:
+            out[name]["roofline"]["traffic"] = tr["traffic_bytes_per_launch"]
+            out[name]["roofline"]["traffic_source"] = os.path.relpath(BATCH_TRAFFIC_FILE,
+                                                                      os.path.dirname(os.path.abspath(__file__)))
         print(f"[bench] batch {name}: {count * M / best:.0f} problem-levels/s ({best * 1e3:.1f} ms), "
-              f"its {its.mean():.2f}, fp64-pc levels {(fb > 0).sum()}, {gbs:.0f} GB/s algorithmic",
+              f"its {its.mean():.2f}, fp64-pc levels {(fb > 0).sum()}, kernel {kern_ms:.1f} ms, "
+              f"{gbs:.0f} GB/s algorithmic",
               file=sys.stderr, flush=True)
         b.close()
     return out
@@ -436,39 +459,53 @@ class Runner:
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "k_levels_n65535_M2048_traffic.json")
+BATCH_TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                  "k_levels_batch256_M256_traffic.json")
 KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2002_11978_amd", "csrc",
                           "fids_kernels.hip")
 
 
-def measured_traffic(n, M):
-    """HBM bytes per launch of the level kernel from the committed counter
+def measured_traffic(n, M, path=TRAFFIC_FILE, form=None, count=None):
+    """HBM bytes per launch of the level kernel from a committed counter
     summary, or None if it is missing, for another workload, or was taken
     from a different kernel source."""
     import hashlib
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
         with open(KERNEL_SRC, "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()
     except OSError:
         return None
-    if t.get("kernel_sha256") != sha or t.get("n") != n or t.get("M") != M:
+    if t.get("kernel_sha256") != sha or t.get("M") != M:
         return None
-    if not str(t.get("form", "")).startswith(FORMS["headline"]["label"]):
+    if count is not None:
+        if t.get("count") != count:
+            return None
+    elif t.get("n") != n:
+        return None
+    if not str(t.get("form", "")).startswith(form or FORMS["headline"]["label"]):
         return None
     return t
 
 
 def profile_pass(args):
-    """Counter pass: one launch of the level kernel (headline form, all M
-    levels, symbols built before it) and one plain device copy of 256 MiB
-    whose FETCH_SIZE / WRITE_SIZE calibrate the counters."""
+    """Counter pass: one plain device copy of 256 MiB whose FETCH_SIZE /
+    WRITE_SIZE calibrate the counters, then one launch of the level kernel
+    over all levels with the symbols built before it (the headline form, or
+    the 256-problem batch in its PCG form).  Every handle is closed before
+    the interpreter shuts down."""
     import torch
     dev = torch.device("cuda:0")
     src = torch.ones(32 << 20, dtype=torch.float64, device=dev)      # 256 MiB
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
+    if args.profile_pass == "batch":
+        profile_batch(args, dev)
+        del src, dst
+        torch.cuda.synchronize()
+        return
     pb = workload(args.n, args.M)
     pb.kappa_d, pb.f_d, pb.phi_d = (torch.from_numpy(a).to(dev) for a in (pb.kappa, pb.f, pb.phi))
     run = Runner(pb, "headline", args.tol, dev)
@@ -477,6 +514,36 @@ def profile_pass(args):
     del src, dst
     torch.cuda.synchronize()
     print(f"[profile-pass] copy 256 MiB, k_levels {ms:.1f} ms", file=sys.stderr, flush=True)
+
+
+def profile_batch(args, dev):
+    """One persistent launch of the 256-problem batch (PCG form, tuned tiles,
+    symbols built first): the launch the batch roofline is computed for."""
+    import torch
+
+    from paper_2002_11978_amd import fids
+    from paper_2002_11978_amd import workloads as W
+    M = 256
+    pbs = [W.batch_member(p, M=M) for p in range(args.batch_count)]
+    arrs = [[torch.from_numpy(getattr(pb, a)).to(dev) for pb in pbs] for a in ("kappa", "f", "phi")]
+    params = [fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=M, r=pb.r, soe_tol=1e-10,
+                                  krylov_tol=args.tol, krylov_maxit=500, solver=2, precision=0, x0_mode=3, precond=2)
+              for pb in pbs]
+    b = fids.Batch(params, *arrs)
+    b.tune(levels=4)
+    b.reset()
+    b.prepare()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    st = b.solve_all_raw(None, None)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    b.close()
+    if st != 0:
+        raise fids.FidsError(st, "fids_batch_solve_all")
+    print(f"[profile-pass] copy 256 MiB, batch launch {e0.elapsed_time(e1):.1f} ms", file=sys.stderr, flush=True)
 
 
 def main():
@@ -564,7 +631,7 @@ def main():
     tr = measured_traffic(pb.n, pb.M) if forms[0] == "headline" else None
     if tr is not None:
         out["roofline"]["traffic"] = tr["traffic_bytes_per_launch"]
-        out["roofline"]["traffic_source"] = os.path.relpath(TRAFFIC_FILE, os.path.dirname(KERNEL_SRC) + "/../..")
+        out["roofline"]["traffic_source"] = os.path.relpath(TRAFFIC_FILE, os.path.dirname(os.path.abspath(__file__)))
     if "plain" in res:
         out["speedup_vs_plain_fp64"] = head["value"] / res["plain"]["value"]
         out["speedup_vs_plain_fp64_kernel"] = res["plain"]["kernel_ms"] / head["kernel_ms"]

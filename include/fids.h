@@ -325,6 +325,10 @@ int fids_batch_solve_all(fids_batch* b, double* const* uT_d, fids_step_info* inf
  * array [members][M] of the reports of every level run so far. */
 int fids_batch_solve_levels(fids_batch* b, int64_t count, double* const* u_d, fids_step_info* info);
 
+/* Builds every member's per-level Strang preconditioner symbols now (as
+ * fids_prepare) instead of inside the next batch step or solve. */
+int fids_batch_prepare(fids_batch* b);
+
 /* Per-member status after the last batch call: status[i] (FIDS_OK or the
  * member's failure; a failed member stops while the others go on) and, if
  * last_level is not NULL, the last level member i completed.  Host arrays of

@@ -1266,6 +1266,14 @@ int fids_batch_solve_levels(fids_batch* b, int64_t count, double* const* u_d, fi
   return FIDS_OK;
 }
 
+int fids_batch_prepare(fids_batch* b) {
+  if (!b) return FIDS_EINVAL;
+  const int st = batch_symbols(b);
+  if (st != FIDS_OK) return st;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return FIDS_OK;
+}
+
 int fids_batch_status(const fids_batch* b, int32_t* status, int64_t* last_level) {
   if (!b || !status) return FIDS_EINVAL;
   std::vector<int> w(size_t(b->count) * 4);

@@ -90,6 +90,7 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_double)]),
     "fids_batch_reset": (ctypes.c_int, [_P]),
+    "fids_batch_prepare": (ctypes.c_int, [_P]),
     "fids_batch_destroy": (ctypes.c_int, [_P]),
     "fids_soe_nodes": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_int32, _D, _D, ctypes.POINTER(ctypes.c_int32)]),
@@ -444,6 +445,9 @@ class Batch:
 
     def reset(self):
         _check(lib().fids_batch_reset(self.h), "fids_batch_reset")
+
+    def prepare(self):
+        _check(lib().fids_batch_prepare(self.h), "fids_batch_prepare")
 
     def close(self):
         if getattr(self, "h", None):

@@ -61,7 +61,21 @@ def test_full_size_levels_satisfy_direct_scheme(recipe, kw, gate):
     say(f"  worst {worst:.2e}")
 
 
-def _check_levels(pb, U, reps, col, levels, gate):
+def _rounding_level(pb, m, col, um, rhs_norm):
+    """Rounding level of a level's FP64 residual relative to ||b||, from the
+    same analysis as the library's acceptance bound: a product with A through
+    length-L FFTs is exact to about u log2(L) ||A||_inf ||x|| (u = 2^-53),
+    scaled by kappa <= kmax, plus u g a_m ||x|| from the shift and u ||b||."""
+    u = 2.0 ** -53
+    L = 1 << int(math.ceil(math.log2(2 * pb.n)))
+    anorm = abs(col[0]) + 2.0 * np.abs(col[1:]).sum()
+    g = 1.0 / math.gamma(1.0 - pb.gamma)
+    beta = g * oracle.l1_weights(pb.T, pb.M, pb.r, pb.gamma, m)[m - 1]
+    kmax = float(np.max(pb.kappa[m - 1]))
+    return u * ((math.log2(L) * kmax * anorm + beta) * float(np.linalg.norm(um)) / rhs_norm + 1.0)
+
+
+def _check_levels(pb, U, reps, col, levels, tol):
     g = 1.0 / math.gamma(1.0 - pb.gamma)
     for m in levels:
         a = oracle.l1_weights(pb.T, pb.M, pb.r, pb.gamma, m)
@@ -70,34 +84,42 @@ def _check_levels(pb, U, reps, col, levels, gate):
             rhs = rhs + g * (np.diff(a)[: m - 1] @ U[1:m])
         lhs = g * a[m - 1] * U[m] + pb.kappa[m - 1] * sla.matmul_toeplitz(col, U[m])
         rel = float(np.linalg.norm(rhs - lhs) / np.linalg.norm(rhs))
-        rep = reps[m - 1].relres
-        say(f"  level {m}: relative residual of the direct scheme {rel:.2e}, true residual the GPU reports {rep:.2e}")
+        e = _rounding_level(pb, m, col, U[m], float(np.linalg.norm(rhs)))
+        accept = max(4.0 * tol, e)            # what the solver may accept (fids.h)
+        # this evaluation differs from the solver's own true residual by the
+        # SOE tolerance (1e-10 relative on the history) and by its own
+        # rounding (scipy's FFTs, the same level e)
+        gate = accept + e + 1e-9
+        rep = reps[m - 1]
+        say(f"  level {m}: direct-scheme residual {rel:.2e}, reported {rep.relres:.2e}, rounding level {e:.2e}, "
+            f"gate {gate:.2e}, flags {rep.flags}")
+        assert rep.relres <= accept, m
+        assert bool(rep.flags & 1) == (rep.relres > tol), m
         assert rel <= gate, m
-        # the solver's own true residual (FIDS system, GPU FFTs) and this one
-        # (direct history, scipy FFTs) agree up to the SOE tolerance and the
-        # rounding of two FP64 evaluations at the floor (measured ratio about 3.4)
-        assert rel <= 5.0 * rep + 1e-9, m
 
 
 # The largest problems the library accepts.  There the attainable FP64
 # residual of a level is no longer the Krylov tolerance: a matvec through
-# FFTs of length L is exact to about eps log2(L) ||kappa|| ||A|| ||u|| (||A||
-# grows like h^{-alpha}), a few 1e-9 of ||b|| at n = 2^20 for these smooth
-# states, so the solvers accept a level at that floor (reported) and the gate
-# is 5e-8 (FP64) / 1e-7 (FP32 preconditioner).
+# FFTs of length L is exact to about u log2(L) kmax ||A||_inf ||u|| (||A||
+# grows like h^{-alpha}); at n = 2^20 - 1 and 2^21 - 1 with alpha = 1.3 that
+# rounding level is 1e-8 - 1e-7 of ||b|| for these states (PCG measured
+# 1.99e-8 at n = 2^20 - 1).  The solvers accept a level at its floor only
+# within max(4 tol, that level) and flag it; the gate of this check is that
+# acceptance bound plus the check's own rounding and the SOE tolerance,
+# computed per level.
 LARGEST = [
-    pytest.param(dict(solver=2, precision=0, x0_mode=3), 5e-8, id="pcg-fp64-x0cubic"),
-    pytest.param(dict(solver=1, precision=0, x0_mode=3), 5e-8, id="fgmres-fp64-x0cubic"),
-    pytest.param(dict(solver=1, precision=1, x0_mode=3), 1e-7, id="mixed-fgmres-fp32pc"),
+    pytest.param(dict(solver=2, precision=0, x0_mode=3), id="pcg-fp64-x0cubic"),
+    pytest.param(dict(solver=1, precision=0, x0_mode=3), id="fgmres-fp64-x0cubic"),
+    pytest.param(dict(solver=1, precision=1, x0_mode=3), id="mixed-fgmres-fp32pc"),
 ]
 
 
-@pytest.mark.parametrize("kw,gate", LARGEST)
+@pytest.mark.parametrize("kw", LARGEST)
 @pytest.mark.parametrize("n", [(1 << 20) - 1, (1 << 21) - 1])
-def test_largest_sizes_satisfy_direct_scheme(n, kw, gate):
+def test_largest_sizes_satisfy_direct_scheme(n, kw):
     """n <= 2^21: embedding 2^22, longest column FFT 2048 points, one column
     per tile, twiddle tables partly in global memory; six levels."""
     pb = W.seeded(1.3, 0.6, n, 6, kappa_seed=11, f_seed=12)
     U, reps = gpu_solve(pb, soe_tol=1e-10, krylov_tol=1e-10, krylov_maxit=500, **kw)
     assert np.isfinite(U).all()
-    _check_levels(pb, U, reps, oracle.ifl_column(n, pb.alpha), range(1, 7), gate)
+    _check_levels(pb, U, reps, oracle.ifl_column(n, pb.alpha), range(1, 7), 1e-10)
