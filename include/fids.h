@@ -268,6 +268,19 @@ int fids_solve_static(const fids_params* p, const double* kappa_d, const double*
 int fids_adjoint(fids_problem* h, const double* dJ_duT_d, double* g_kappa_d,
                  double* g_f_d, double* g_phi_d);
 
+/* The level-m Strang preconditioner as the device builds it (eq. 4.3):
+ * P_m = b_m' I + kbar_m s(A), kbar_m the mean of kappa^m and s(A) Strang's
+ * circulant of A.  q (host, [n], may be NULL) receives the first column of
+ * the n x n circulant P_m^{-1} (a length-n DFT of 1 / (b_m' + kbar_m lam_k)
+ * by Bluestein's method; e_0 for FIDS_NONE), which is symmetric, so P_m^{-1}
+ * is also the symmetric Toeplitz matrix with first column q; qhat (host,
+ * [L/2 + 1], may be NULL) receives the real spectrum of its length-L
+ * circulant embedding [q_0, ..., q_{n-1}, 0, ..., 0, q_{n-1}, ..., q_1]
+ * through which the solver applies P_m^{-1} (qhat[k] = sum_i e_i
+ * cos(2 pi i k / L)).  Rebuilds level m's symbol in place (same values);
+ * synchronous; FIDS_EINVAL for m outside 1..M.  For checking. */
+int fids_precond_symbol(fids_problem* h, int64_t m, double* q, double* qhat);
+
 /* Host copy of the per-level reports of the last fids_adjoint's transposed
  * solves (M entries, index m-1; relres relative to ||K_m ubar^m||). */
 int fids_adjoint_report(const fids_problem* h, fids_step_info* per_step);

@@ -1061,6 +1061,28 @@ int fids_adjoint(fids_problem* h, const double* dJ_duT_d, double* g_kappa_d, dou
   return FIDS_OK;
 }
 
+int fids_precond_symbol(fids_problem* h, int64_t m, double* q, double* qhat) {
+  if (!h || m < 1 || m > h->sh.M) return FIDS_EINVAL;
+  const int n = int(h->sh.n), Nc = int(h->sh.Nc);
+  // level m's kbar and symbol alone, with the kernels the solves use (the
+  // values are the same whichever batch of levels builds them)
+  HIPCHK(fids::launch_kbar(h->hp.kappa, n, int(m), 1, h->prm.kappa_time_dependent, at<double>(h->ws, h->lo.kbar),
+                           at<double>(h->ws, h->lo.kmax), h->stream));
+  HIPCHK(fids::launch_symbols(h->hj, h->dj, int(m), 1, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (q) {
+    if (h->hj.identity) {
+      for (int i = 0; i < n; ++i) q[i] = i == 0 ? 1.0 : 0.0;
+    } else {
+      HIPCHK(hipMemcpy(q, h->hj.q, size_t(n) * sizeof(double), hipMemcpyDeviceToHost));
+    }
+  }
+  if (qhat)
+    HIPCHK(hipMemcpy(qhat, h->hp.qhat + size_t(m) * size_t(Nc + 1), size_t(Nc + 1) * sizeof(double),
+                     hipMemcpyDeviceToHost));
+  return FIDS_OK;
+}
+
 int fids_adjoint_report(const fids_problem* h, fids_step_info* per_step) {
   if (!h || !per_step) return FIDS_EINVAL;
   if (!h->dpa) return FIDS_ESTATE;

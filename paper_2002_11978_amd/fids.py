@@ -70,6 +70,7 @@ _SIGS = {
     "fids_solve_static": (ctypes.c_int, [ctypes.POINTER(Params), _P, _P, _P, _P, ctypes.POINTER(StepInfo), _P]),
     "fids_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "fids_adjoint_report": (ctypes.c_int, [_P, ctypes.POINTER(StepInfo)]),
+    "fids_precond_symbol": (ctypes.c_int, [_P, ctypes.c_int64, _D, _D]),
     "fids_reset": (ctypes.c_int, [_P]),
     "fids_prepare": (ctypes.c_int, [_P]),
     "fids_destroy": (ctypes.c_int, [_P]),
@@ -344,6 +345,18 @@ class Problem:
 
     def prepare(self):
         _check(lib().fids_prepare(self.h), "fids_prepare")
+
+    def precond_symbol(self, m):
+        """(q, qhat) of level m's Strang preconditioner as built on the device (host arrays)."""
+        import numpy as np
+        L = 1
+        while L < 2 * self.n:
+            L *= 2
+        L = max(L, 4)
+        q = np.zeros(self.n)
+        qhat = np.zeros(L // 2 + 1)
+        _check(lib().fids_precond_symbol(self.h, m, _dptr(q), _dptr(qhat)), "fids_precond_symbol")
+        return q, qhat
 
     def close(self):
         if getattr(self, "h", None):
