@@ -716,7 +716,37 @@ bool schedule_at(double T, const std::vector<double>& c, const std::vector<int>&
   return true;
 }
 
-std::vector<Slot> schedule_batch(const std::vector<double>& c, const std::vector<int>& kmax, int R) {
+// Workgroups the schedule leaves free go to the members that already have a
+// group of several workgroups, heaviest first (prio: the SOE history's size
+// n N_exp, which the length-L cost leaves out): each doubling that fits.
+// A group of k > 1 costs more than the model's c / k + overhead (on MI355X a
+// two-workgroup member with L = 32768 took 1.56x the level time of a
+// one-workgroup member with L = 16384), so these members set the makespan
+// and the free workgroups shorten it.
+void upgrade_groups(std::vector<Slot>& out, const std::vector<int>& kmax, const std::vector<double>& prio, int R) {
+  int used = 0;
+  for (const Slot& sl : out) used += sl.ng;
+  std::vector<size_t> cand;
+  for (size_t k = 0; k < out.size(); ++k)
+    if (out[k].ng > 1 && out[k].members.size() == 1) cand.push_back(k);
+  std::stable_sort(cand.begin(), cand.end(), [&](size_t a, size_t b) {
+    return prio[size_t(out[a].members[0])] > prio[size_t(out[b].members[0])];
+  });
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (size_t k : cand) {
+      Slot& sl = out[k];
+      if (2 * sl.ng <= kmax[size_t(sl.members[0])] && used + sl.ng <= R) {
+        used += sl.ng;
+        sl.ng *= 2;
+        changed = true;
+      }
+    }
+  }
+}
+
+std::vector<Slot> schedule_batch(const std::vector<double>& c, const std::vector<int>& kmax, int R,
+                                 const std::vector<double>* prio = nullptr) {
   double lo = 0.0, hi = 0.0;
   for (size_t i = 0; i < c.size(); ++i) {
     double best = c[i];
@@ -731,13 +761,15 @@ std::vector<Slot> schedule_batch(const std::vector<double>& c, const std::vector
     for (size_t i = 0; i < c.size(); ++i) out[0].members.push_back(int(i));
     return out;
   }
-  if (schedule_at(lo, c, kmax, R, &out)) return out;
-  for (int it = 0; it < 60; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (schedule_at(mid, c, kmax, R, nullptr)) hi = mid;
-    else lo = mid;
+  if (!schedule_at(lo, c, kmax, R, &out)) {
+    for (int it = 0; it < 60; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (schedule_at(mid, c, kmax, R, nullptr)) hi = mid;
+      else lo = mid;
+    }
+    schedule_at(hi, c, kmax, R, &out);
   }
-  schedule_at(hi, c, kmax, R, &out);
+  if (prio) upgrade_groups(out, kmax, *prio, R);
   return out;
 }
 
@@ -746,15 +778,17 @@ std::vector<Slot> schedule_batch(const std::vector<double>& c, const std::vector
 // bound on the level kernel's LDS (one-workgroup plans have the largest tiles)
 // with a descriptor for the occupancy query.
 int batch_costs(const fids_params* p, int32_t count, std::vector<double>& cost, std::vector<int>& kmax,
-                size_t* lds_bound, Prob* probe) {
+                size_t* lds_bound, Prob* probe, std::vector<double>* prio = nullptr) {
   cost.assign(size_t(count), 0.0);
   kmax.assign(size_t(count), 1);
+  if (prio) prio->assign(size_t(count), 0.0);
   for (int32_t i = 0; i < count; ++i) {
     fids_params q = p[i];
     batch_params(q, 1);
     Shapes sh;
     if (shapes_of(q, sh, nullptr) != FIDS_OK) return FIDS_EINVAL;
     cost[size_t(i)] = double(sh.L);
+    if (prio) (*prio)[size_t(i)] = double(sh.n) * double(sh.nexp);
     int k = 1;
     while (k * 2 <= std::min(64, sh.pr.N2) && int64_t(k) * 2 * 1024 <= sh.Nc) k *= 2;
     kmax[size_t(i)] = k;
@@ -1128,7 +1162,8 @@ int fids_batch_init(const fids_params* p, int32_t count, const double* const* ka
   std::vector<int> kmax;
   size_t lds_bound = 0;
   Prob probe{};
-  if (batch_costs(p, count, cost, kmax, &lds_bound, &probe) != FIDS_OK) return fail(FIDS_EINVAL);
+  std::vector<double> prio;
+  if (batch_costs(p, count, cost, kmax, &lds_bound, &probe, &prio) != FIDS_OK) return fail(FIDS_EINVAL);
   // graph mode: one workgroup per member, so that every level is an ordinary
   // launch a HIP graph can hold (a group of several workgroups needs a
   // cooperative launch)
@@ -1146,7 +1181,7 @@ int fids_batch_init(const fids_params* p, int32_t count, const double* const* ka
       return fail(FIDS_EDEVICE);
     resident = std::max(1, cus * per_cu);
   }
-  const std::vector<Slot> slots = schedule_batch(cost, kmax, resident);
+  const std::vector<Slot> slots = schedule_batch(cost, kmax, resident, &prio);
   b->hprobs.resize(size_t(count));
   b->members.assign(size_t(count), nullptr);
   b->groups.assign(size_t(count), 1);
@@ -1318,8 +1353,9 @@ int fids_batch_plan(const fids_params* p, int32_t count, int32_t resident, int32
   if (!p || count < 1 || resident < 1 || !ng || !slot) return FIDS_EINVAL;
   std::vector<double> cost;
   std::vector<int> kmax;
-  if (batch_costs(p, count, cost, kmax, nullptr, nullptr) != FIDS_OK) return FIDS_EINVAL;
-  const std::vector<Slot> slots = schedule_batch(cost, kmax, resident);
+  std::vector<double> prio;
+  if (batch_costs(p, count, cost, kmax, nullptr, nullptr, &prio) != FIDS_OK) return FIDS_EINVAL;
+  const std::vector<Slot> slots = schedule_batch(cost, kmax, resident, &prio);
   double worst = 0.0;
   for (size_t k = 0; k < slots.size(); ++k) {
     double load = 0.0;
