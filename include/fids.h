@@ -133,9 +133,12 @@ typedef struct fids_params {
     int32_t precond;      /* FIDS_STRANG | FIDS_NONE | FIDS_STRANG_K               */
     int32_t kappa_time_dependent; /* 1: kappa_d is [M][n]; 0: kappa_d is [n]      */
     int32_t x0_mode;      /* 0: zero initial guess (Sec. 5); k = 1, 2, 3:          */
-                          /* polynomial extrapolation of degree k on the graded    */
-                          /* mesh through u^{m-1}, ..., u^{m-1-k} (lower degree    */
-                          /* where fewer levels exist)                             */
+                          /* polynomial extrapolation of degree k in t^gamma       */
+                          /* through u^{m-1}, ..., u^{m-1-k} (lower degree where   */
+                          /* fewer levels exist; the solution's leading term near  */
+                          /* t = 0, u^0 + c t^gamma, is linear in t^gamma); the    */
+                          /* adjoint extrapolates its solutions backward the same  */
+                          /* way                                                   */
     int32_t store_states; /* 1: keep every u^m in the workspace (fids_adjoint     */
                           /* then needs no recomputation); 0: keep only what       */
                           /* stepping needs                                        */

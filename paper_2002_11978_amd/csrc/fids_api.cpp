@@ -83,7 +83,7 @@ int env_int(const char* name, int dflt) {
 // Workspace layout of one problem.  Offsets are bytes from ws_d.
 struct Layout {
   size_t prob, job, abort_, status, bar, info, part;
-  size_t beta, theta, decay, gw, ahat, lam, chirp, chirp_hat, kbar, kmax;
+  size_t beta, theta, decay, gw, ahat, lam, chirp, chirp_hat, kbar, kmax, xv;
   size_t tw1r, tw1rf, tw2r, tw2rf, tw1c, tw1cf, tw2c, tw2cf, twlo, twlof, twhi, twhif;
   size_t qhat, qhatf;
   size_t Tb, q, Tq;
@@ -134,6 +134,7 @@ Layout make_layout(const fids_params& p, const Shapes& sh, size_t sym_budget = k
   lo.beta = take((M + 1) * 8);
   lo.tau = take((M + 1) * 8);
   lo.soec = take((M + 1) * 8);
+  lo.xv = take((M + 1) * 8);
   // synchronisation words on separate 4 KiB pages (separate memory channels)
   off = (off + 4095) / 4096 * 4096;
   lo.sync2 = take(4096);
@@ -491,6 +492,7 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   st |= upload(h, lo.beta, t.beta.data(), t.beta.size() * 8);
   st |= upload(h, lo.tau, t.tau.data(), t.tau.size() * 8);
   st |= upload(h, lo.soec, t.soec.data(), t.soec.size() * 8);
+  st |= upload(h, lo.xv, t.xv.data(), t.xv.size() * 8);
   st |= upload(h, lo.theta, t.theta.data(), t.theta.size() * 8);
   st |= upload(h, lo.decay, t.decay.data(), t.decay.size() * 8);
   st |= upload(h, lo.gw, t.gw.data(), t.gw.size() * 8);
@@ -534,6 +536,7 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   hp.AU = at<double>(ws, lo.AU);
   hp.sync2 = at<unsigned>(ws, lo.sync2);
   hp.hflag = at<unsigned>(ws, lo.hflag);
+  hp.xv = at<double>(ws, lo.xv);
   hp.beta = at<double>(ws, lo.beta); hp.tau = at<double>(ws, lo.tau); hp.theta = at<double>(ws, lo.theta); hp.decay = at<double>(ws, lo.decay);
   hp.gw = at<double>(ws, lo.gw); hp.ahat = at<double>(ws, lo.ahat);
   hp.qhat = lo.qhat ? at<double>(ws, lo.qhat) : nullptr;

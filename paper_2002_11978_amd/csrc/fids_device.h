@@ -81,6 +81,7 @@ struct Prob {
   // set-up tables
   const double* beta;           // [M+1]
   const double* tau;            // [M+1] tau_m = t_m - t_{m-1}
+  const double* xv;             // [M+1] (t_m / T)^gamma, the initial guess's extrapolation coordinate
   const double* theta;          // [(M+1) * nexp]
   const double* decay;          // [(M+1) * nexp]
   const double* gw;             // [nexp]

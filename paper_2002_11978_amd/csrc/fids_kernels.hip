@@ -732,9 +732,10 @@ __device__ __forceinline__ int helper_loop(const Prob& p, int hr, int k0, int k1
   return FIDS_OK;
 }
 
-// Lagrange weights at t of polynomial extrapolation through npts earlier
-// levels at distances d_k = t - t_k > 0 (k = 1..npts, nearest first):
-// w_k = prod_{j != k} d_j / (d_j - d_k).
+// Lagrange weights at v of polynomial extrapolation through npts earlier
+// levels at distances d_k = v - v_k > 0 (k = 1..npts, nearest first):
+// w_k = prod_{j != k} d_j / (d_j - d_k).  Forward and adjoint solves
+// extrapolate in v = (t / T)^gamma (the adjoint backward in time).
 __device__ __forceinline__ void extrap_weights(const double* d, int npts, double* w) {
   for (int k = 0; k < kRing; ++k) {
     double v = 0.0;
@@ -751,8 +752,9 @@ __device__ __forceinline__ void extrap_weights(const double* d, int npts, double
 //   b = b_m' u^{m-1} - h^m + f^m,  h^m = sum_j g w_j F_j^{(m)};
 // with helpers h^m = H1^m + c_m (u^{m-1} - u^{m-2}); without them the solver
 // group advances F here.  kappa^m is copied tile-major.
-// Initial guess x0 = 0, or polynomial extrapolation on the graded mesh through
-// the last x0_mode + 1 states (linear, quadratic, cubic; fewer near m = 1).
+// Initial guess x0 = 0, or polynomial extrapolation in v = (t / T)^gamma
+// through the last x0_mode + 1 states (linear, quadratic, cubic; fewer near
+// m = 1): the solution behaves like u^0 + c t^gamma near t = 0, linear in v.
 // Then one of
 //   fused (FGMRES, x0_mode >= 1, m >= 3): A x0 = sum_k w_k A u^{m-k} from the
 //     stored products, r0 = b - b_m' x0 - kappa .* A x0, partials (b,b),
@@ -781,7 +783,8 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
   }
   const double bm = p.beta[m];
   const double cm = p.soec[m];
-  const double rho = (m >= 2) ? p.tau[m] / p.tau[m - 1] : 0.0;
+  // extrapolation coordinate v_m = (t_m / T)^gamma (linear through two levels: x0 = u^{m-1} + rho d)
+  const double rho = (m >= 2) ? (p.xv[m] - p.xv[m - 1]) / (p.xv[m - 1] - p.xv[m - 2]) : 0.0;
   const bool warm = p.x0_mode != 0;
   const bool bicg = p.solver == FIDS_BICGSTAB;
   const double* um1 = p.u[(m - 1) % kRing];
@@ -798,11 +801,8 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
   double w[kRing];
   {
     double d[kRing];
-    double acc_t = 0.0;
-    for (int k = 0; k < kRing; ++k) {
-      acc_t += (m - k >= 1) ? p.tau[m - k] : 0.0;
-      d[k] = acc_t;                        // t_m - t_{m-1-k}
-    }
+    for (int k = 0; k < kRing; ++k)
+      d[k] = (m - 1 - k >= 0) ? p.xv[m] - p.xv[m - 1 - k] : 1.0;   // v_m - v_{m-1-k} (used for k < npts)
     extrap_weights(d, npts, w);
   }
   const int blk = 2 * pl.CT * pl.N1;
@@ -1034,17 +1034,13 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
   const double* y1 = p.u[(m + 1) % kRing];
   const double* y2 = p.u[(m + 2) % kRing];
   double* x = p.u[m % kRing];
-  const double rho = (m + 2 <= p.M) ? p.tau[m + 1] / p.tau[m + 2] : 0.0;
-  // backward in time: y^{m+1}, ..., y^{m+npts} at distances t_{m+k} - t_m
+  const double rho = (m + 2 <= p.M) ? (p.xv[m + 1] - p.xv[m]) / (p.xv[m + 2] - p.xv[m + 1]) : 0.0;
+  // backward in time: y^{m+1}, ..., y^{m+npts} at distances v_{m+k} - v_m
   const int npts = !warm ? 0 : min(p.x0_mode + 1, p.M - m);
   double w[kRing];
   {
     double d[kRing];
-    double acc_t = 0.0;
-    for (int k = 0; k < kRing; ++k) {
-      acc_t += (m + 1 + k <= p.M) ? p.tau[m + 1 + k] : 0.0;
-      d[k] = acc_t;
-    }
+    for (int k = 0; k < kRing; ++k) d[k] = (m + 1 + k <= p.M) ? p.xv[m + 1 + k] - p.xv[m] : 1.0;
     extrap_weights(d, npts, w);
   }
   const double* km = p.kappa + (p.kappa_td ? size_t(m - 1) * p.n : 0);

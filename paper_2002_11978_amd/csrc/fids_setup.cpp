@@ -361,6 +361,11 @@ int build_tables(const fids_params& p, HostTables& t) {
   t.Nc = t.L / 2;
   t.g = 1.0 / std::tgamma(1.0 - p.gamma);
   t.tau = step_sizes(p.T, p.M, p.r);
+  // The solution of (1.1) starts as u^0 + c t^gamma + ... (the weak
+  // singularity the graded mesh resolves), which is linear in t^gamma: the
+  // extrapolated initial guess is a polynomial in this coordinate.
+  t.xv.assign(size_t(p.M) + 1, 0.0);
+  for (int64_t m = 1; m <= p.M; ++m) t.xv[size_t(m)] = std::pow(double(m) / double(p.M), p.r * p.gamma);
   t.beta.assign(p.M + 1, 0.0);
   const double g2 = std::tgamma(2.0 - p.gamma);
   for (int64_t m = 1; m <= p.M; ++m) t.beta[m] = std::pow(t.tau[m], -p.gamma) / g2;

@@ -29,6 +29,7 @@ struct HostTables {
   int nexp = 0;         // SOE node count
   double g = 0;         // 1 / Gamma(1 - gamma)
   std::vector<double> tau;     // [M+1], tau[m] = t_m - t_{m-1}, tau[0] = 0
+  std::vector<double> xv;      // [M+1], (t_m / T)^gamma: the coordinate of the extrapolated initial guess
   std::vector<double> beta;    // [M+1], beta[m] = g a_m^{(m)} = tau_m^{-gamma}/Gamma(2-gamma)
   std::vector<double> theta;   // [(M+1) * nexp], recurrence input factor (m >= 2)
   std::vector<double> decay;   // [(M+1) * nexp], e^{-s_j tau_m}
