@@ -126,7 +126,7 @@ Layout make_layout(const fids_params& p, const Shapes& sh, size_t sym_budget = k
   lo.job = take(sizeof(SymJob));
   lo.abort_ = take(sizeof(int));
   lo.status = take(4 * sizeof(int));
-  lo.bar = take(4096);
+  lo.bar = take(fids::kBarBytes);
   lo.info = take(M * sizeof(fids_step_info));
   // partial sums: one slot per column tile; sized for the finest split (CT = 1)
   // so that the layout does not depend on the group size a batch assigns
@@ -392,7 +392,7 @@ int launch_wait(fids_problem* h, const Prob& hd, Prob* d, int m_begin, int m_end
   HIPCHK(hipStreamSynchronize(h->stream));
   if (stat[0] == FIDS_EDEVICE) {
     // a group barrier timed out: clear the barrier words for the next launch
-    HIPCHK(hipMemsetAsync(hd.bar, 0, 4 * sizeof(unsigned), h->stream));
+    HIPCHK(hipMemsetAsync(hd.bar, 0, fids::kBarBytes, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
   }
   return FIDS_OK;
@@ -529,8 +529,9 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   hp.slot_first = 0;
   // one workgroup per column tile or row group, up to the group size (a
   // workgroup runs several tiles in turn where the LDS tile cap forces more
-  // tiles than that; sums stay per tile, so the result does not depend on ng)
-  hp.ng = std::max(1, std::min(std::max(hp.pl.ntiles, hp.pl.nrg), h->sh.grp));
+  // tiles than that; sums stay per tile, so the result does not depend on ng);
+  // at most kMaxGroup, the arrival slots of the group barrier
+  hp.ng = std::max(1, std::min({std::max(hp.pl.ntiles, hp.pl.nrg), h->sh.grp, fids::kMaxGroup}));
   hp.soec = at<double>(ws, lo.soec);
   hp.H1 = at<double>(ws, lo.H1);
   hp.AU = at<double>(ws, lo.AU);
@@ -992,7 +993,7 @@ int fids_reset(fids_problem* h) {
   HIPCHK(hipMemsetAsync(h->hp.sync2, 0, 4096, h->stream));
   HIPCHK(hipMemsetAsync(h->hp.hflag, 0, 4096 * 64, h->stream));
   HIPCHK(hipMemsetAsync(h->hp.status, 0, 4 * sizeof(int), h->stream));
-  HIPCHK(hipMemsetAsync(h->hp.bar, 0, 4 * sizeof(unsigned), h->stream));
+  HIPCHK(hipMemsetAsync(h->hp.bar, 0, fids::kBarBytes, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   h->level = 0;
   h->poisoned = false;
@@ -1425,7 +1426,7 @@ int fids_batch_tune(fids_batch* b, int32_t levels, int32_t* tile_ct) {
       HIPCHK(fids::launch_init_state(trial, rep_h->dp, b->stream));
       HIPCHK(hipMemsetAsync(trial.F, 0, size_t(trial.nexp) * trial.vlen * 8, b->stream));
       HIPCHK(hipMemsetAsync(trial.AU, 0, size_t(fids::kRing) * trial.vlen * 8, b->stream));
-      HIPCHK(hipMemsetAsync(trial.bar, 0, 4 * sizeof(unsigned), b->stream));
+      HIPCHK(hipMemsetAsync(trial.bar, 0, fids::kBarBytes, b->stream));
       if (c.lds > 65536) HIPCHK(fids::set_level_lds_limit(trial, c.lds));
       HIPCHK(hipEventRecord(e0, b->stream));
       if (ng > 1) {
@@ -1489,7 +1490,7 @@ int fids_batch_reset(fids_batch* b) {
     HIPCHK(fids::launch_init_state(h->hp, h->dp, b->stream));
     HIPCHK(hipMemsetAsync(h->hp.F, 0, size_t(h->hp.nexp) * h->hp.vlen * 8, b->stream));
     HIPCHK(hipMemsetAsync(h->hp.AU, 0, size_t(fids::kRing) * h->hp.vlen * 8, b->stream));
-    HIPCHK(hipMemsetAsync(h->hp.bar, 0, 4 * sizeof(unsigned), b->stream));
+    HIPCHK(hipMemsetAsync(h->hp.bar, 0, fids::kBarBytes, b->stream));
     h->sym_hi = 0;
   }
   HIPCHK(hipMemsetAsync(b->dstatus, 0, size_t(b->count) * 4 * sizeof(int), b->stream));

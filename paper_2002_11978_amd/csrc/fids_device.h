@@ -25,6 +25,9 @@ constexpr double kPcgSlack = 4.0; // PCG accepts a true residual up to this many
 constexpr int kVecBatch = 2;      // solver element items per thread whose loads are issued together
 constexpr int kMaxHelpers = 1024; // helper workgroups (one release-flag line each)
 constexpr int kDirectChunks = 128; // direct history: most state chunks per element block
+constexpr int kBarSlotWords = 32;  // group barrier: one 128-byte arrival slot per workgroup
+constexpr int kMaxGroup = 256;     // workgroups of one problem (one co-resident workgroup per CU)
+constexpr size_t kBarBytes = size_t(kMaxGroup) * kBarSlotWords * sizeof(unsigned);
 
 // Direct history with helpers: state chunks for nh helpers over problems of n
 // unknowns (element blocks of kThreads value pairs).
@@ -111,7 +114,7 @@ struct Prob {
   double* part;                 // [SL_COUNT][ntiles]
   fids_step_info* info;         // [M]
   int* status;                  // [4]: status, last completed level, stop flag
-  unsigned* bar;                // [2] group barrier {count, generation}
+  unsigned* bar;                // group barrier: generation of workgroup r at bar[r * kBarSlotWords]
   // SOE helpers: nh workgroups stream the history one level ahead
   int nh;                       // helper workgroups (0: the solver group streams F itself)
   const double* soec;           // [M+1] c_m = sum_j g w_j theta_{m,j}

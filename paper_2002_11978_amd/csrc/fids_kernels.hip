@@ -389,46 +389,55 @@ __device__ __forceinline__ void write_partials(const Prob& p, int tile, const in
 }
 
 // ------------------------------------------------------------- group barrier
-// All workgroups of one problem meet here.  Thread 0 publishes the
-// workgroup's writes with an agent-scope release fence and arrives on a
-// counter with a relaxed add; the last to arrive takes an acquire fence (its
-// add reads the release sequence of every earlier arrival), resets the
-// counter and advances the generation with a release store.  The others poll
-// the generation with relaxed loads and take one acquire fence once it has
-// moved: on gfx950 every agent-scope acquire invalidates the caches, so an
-// acquiring poll loop would do that on every probe (measured on MI355X: 8.1
-// against 5.2 us per phase for 64 workgroups exchanging 16 KiB each).  A
-// wall-clock timeout or an abort raised by another workgroup makes every
-// waiter return false, so the launch always drains.
-__device__ __forceinline__ bool group_barrier(const Prob& p, unsigned& gen, unsigned long long timeout,
+// All workgroups of one problem meet here.  Every workgroup owns one 128-byte
+// arrival slot holding the number of barriers it has reached.  Thread 0
+// publishes the workgroup's writes with an agent-scope release fence and
+// stores the new count into its own slot (a plain relaxed store: no
+// read-modify-write, so arrivals do not queue behind one another on a shared
+// counter); wave 0 then polls every slot of the group with relaxed loads, one
+// per lane, until all have reached that count, and takes one acquire fence
+// (on gfx950 every agent-scope acquire invalidates the caches, so polling
+// with acquiring loads would do that on every probe).  Measured on MI355X
+// with 64 workgroups exchanging 16 KiB each: 3.6 us per phase against 5.2 us
+// for a counter with a generation word, 2.1 against 3.4 us with no data.
+// The counts only grow, so a workgroup that has already moved on to the next
+// barrier still satisfies the test of this one.  A wall-clock timeout or an
+// abort raised by another workgroup makes every waiter return false, so the
+// launch always drains.
+__device__ __forceinline__ bool group_barrier(const Prob& p, int rank, unsigned& gen, unsigned long long timeout,
                                               int* abort_flag) {
   __shared__ int s_ok;
   __syncthreads();
   if (p.ng == 1) return true;
-  if (threadIdx.x == 0) {
+  const unsigned g = gen + 1u;
+  gen = g;
+  if (threadIdx.x < 64) {   // wave 0
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&p.bar[rank * kBarSlotWords], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     int ok = 1;
-    const unsigned g = gen;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned prev = __hip_atomic_fetch_add(&p.bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == unsigned(p.ng - 1)) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      __hip_atomic_store(&p.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&p.bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      const unsigned long long t0 = wall_clock64();
-      while (__hip_atomic_load(&p.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        __builtin_amdgcn_s_sleep(1);
-        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
-        if (wall_clock64() - t0 > timeout) {
+    const unsigned long long t0 = wall_clock64();
+    for (;;) {
+      bool here = true;
+      for (int i = threadIdx.x; i < p.ng; i += 64)
+        here &= int(__hip_atomic_load(&p.bar[i * kBarSlotWords], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - g) >= 0;
+      if (__all(here)) break;
+      __builtin_amdgcn_s_sleep(1);
+      // the decision to give up is lane 0's, taken by the whole wave
+      int stop = 0;
+      if (threadIdx.x == 0) {
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          stop = 1;
+        } else if (wall_clock64() - t0 > timeout) {
           __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ok = 0;
-          break;
+          stop = 1;
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (__builtin_amdgcn_readfirstlane(stop)) { ok = 0; break; }
     }
-    gen = g + 1u;
-    s_ok = ok;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x == 0) s_ok = ok;
   }
   __syncthreads();
   return s_ok != 0;
@@ -525,7 +534,8 @@ template <> __device__ __forceinline__ double2 z_put<float>(const Prob& p, int i
 enum { VB = 0, VR, VRH, VP, VV, VS, VT, VPH, VSH };
 
 struct Ctl {
-  unsigned gen;
+  int rank;        // this workgroup's place in its problem's group
+  unsigned gen;    // group barriers this workgroup has passed (its arrival slot)
   unsigned long long timeout;
   int* abort_flag;
   int hist_lo;     // >= 0: store u^k at uhist[k - hist_lo]; < 0: keep no states
@@ -550,7 +560,7 @@ template <> __device__ __forceinline__ float2* lbuf<float>(const Lds& L) { retur
 
 #define BARRIER()                                                     \
   do {                                                                \
-    if (!group_barrier(p, ctl.gen, ctl.timeout, ctl.abort_flag)) {    \
+    if (!group_barrier(p, ctl.rank, ctl.gen, ctl.timeout, ctl.abort_flag)) { \
       return FIDS_EDEVICE;                                            \
     }                                                                 \
   } while (0)
@@ -2198,13 +2208,15 @@ __device__ __forceinline__ void run_member(const Prob& p, int rank, int m_begin,
     __syncthreads();
   }
   Ctl ctl;
-  ctl.gen = 0;
+  ctl.rank = rank;
+  // every workgroup of the group ends a launch with the same count
+  ctl.gen = rank < p.ng ? __hip_atomic_load(&p.bar[rank * kBarSlotWords], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                        : 0u;
   ctl.timeout = timeout;
   ctl.abort_flag = abort_flag;
   ctl.hist_lo = hist_lo;
   ctl.ckpt_on = ckpt_on;
   ctl.pending = 0;
-  if (threadIdx.x == 0) ctl.gen = __hip_atomic_load(&p.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if constexpr (ADJ) {
     for (int m = m_begin; m >= m_end; --m) {
       ctl.pending = m < m_begin;
