@@ -121,6 +121,41 @@ def test_batch_graph_mode_equals_persistent():
     g.close()
 
 
+def test_batch_graph_mode_tuned_after_capture():
+    """A solve in graph mode captures the level launches with the plan's tile
+    shape and LDS size; tuning afterwards changes both, so the next solve
+    must capture again rather than replay the old graph.  Its answer is
+    compared with a persistent-mode batch tuned the same way (the tuner may
+    pick another tiling there, so the comparison allows summation-order
+    differences), and with the untuned graph-mode answer."""
+    pbs = [W.seeded(1.5, 0.4, 1000, 10, kappa_seed=320 + i, f_seed=420 + i) for i in range(4)]
+    p = _batch(pbs, **MIXED)
+    p.tune()
+    ref = [o.cpu().numpy() for o in p.solve_all()[0]]
+    p.close()
+    # the graph-mode batch starts from 4 column tiles of 8 columns (N_c = 1024
+    # = 32 x 32), which the tuner is expected to replace
+    os.environ["FIDS_BATCH_MODE"] = "graph"
+    os.environ["FIDS_TILES"] = "4"
+    try:
+        g = _batch(pbs, **MIXED)
+    finally:
+        del os.environ["FIDS_BATCH_MODE"]
+        del os.environ["FIDS_TILES"]
+    first = [o.cpu().numpy() for o in g.solve_all()[0]]   # captured with the untuned plan
+    g.reset()
+    ct = g.tune()
+    say(f"graph-mode batch tuned after capture: columns per tile 8 -> {list(ct)}")
+    for rep in range(2):
+        outs = [o.cpu().numpy() for o in g.solve_all()[0]]
+        for a, b0, o in zip(ref, first, outs):
+            assert np.isfinite(o).all()
+            assert rel_maxnorm(o, a) <= 1e-10
+            assert rel_maxnorm(o, b0) <= 1e-10
+        g.reset()
+    g.close()
+
+
 def test_failing_member_does_not_stop_the_others():
     pbs = _mixed_members(6)
     params = [_params(pb, **MIXED) for pb in pbs]
