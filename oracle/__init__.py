@@ -23,3 +23,7 @@ from .fids_oracle import (  # noqa: F401
     strang_column, dids_solve, dids_adjoint, errors,
     soe_relative_error, fids_history_weights,
 )
+from .ifl2d import (  # noqa: F401
+    c2_alpha, corner_integral, cell_integrals, node_weights, exterior_integral, lattice_error, mu_star,
+    ifl2d_coefficients, ifl2d_matrix, ifl2d_apply_at, grid as grid2d, dids2d_solve,
+)

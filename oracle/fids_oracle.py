@@ -126,16 +126,18 @@ def _kappa_row(kappa, m):
     return kappa[m - 1] if kappa.ndim == 2 else kappa
 
 
-def dids_solve(alpha, gamma, n, M, r, kappa, f, phi, l=1.0, T=1.0, mu=None):
+def dids_solve(alpha, gamma, n, M, r, kappa, f, phi, l=1.0, T=1.0, mu=None, matrix=None):
     """Direct implicit difference scheme, matrix form (4.1), dense LU per level.
 
     For m = 1..M:
       rhs = g [a_1^{(m)} u^0 + sum_{k=1}^{m-1} (a_{k+1}^{(m)} - a_k^{(m)}) u^k] + f^m
       (g a_m^{(m)} I + K^{(m)} A) u^m = rhs,   K^{(m)} = diag(kappa(x_i, t_m)).
     The solve is LAPACK gesv (the paper's direct solver is MATLAB's backslash).
+    A is the matrix of eq. (3.16x), or `matrix` when given (the 2-D operator of
+    ``oracle.ifl2d``, n then being the number of unknowns).
     Returns U with U[m] = u^m, m = 0..M.
     """
-    A = ifl_matrix(n, alpha, l, mu)
+    A = ifl_matrix(n, alpha, l, mu) if matrix is None else matrix
     g = 1.0 / math.gamma(1.0 - gamma)
     U = np.empty((M + 1, n))
     U[0] = phi
