@@ -160,6 +160,19 @@ typedef struct fids_params {
                           /* F^{(m-1)}) at levels m = kC + 1 and fids_adjoint      */
                           /* recomputes each segment of C levels from its          */
                           /* snapshot, bit for bit; 0: no snapshots                */
+    int32_t dims;         /* spatial dimensions: 1 (the paper's problem) or 2, the */
+                          /* multi-dimensional case its Sec. 6 names: the square   */
+                          /* (-l, l)^2 with n interior nodes per axis, so that      */
+                          /* kappa_d is [M][n*n] (or [n*n]), f_d [M][n*n], phi_d    */
+                          /* and every state [n*n], node (i, j) (x index i) at     */
+                          /* i + n j; the IFL matrix is the 2-D form of eq.        */
+                          /* (3.16x) (block Toeplitz with Toeplitz blocks; see     */
+                          /* fids_ifl2d_coefficients), applied through a padded    */
+                          /* 1-D layout of rows of stride S = the smallest power   */
+                          /* of two >= 2n - 1, so that S (n - 1) + n <= 2^21;      */
+                          /* mu 0 selects the 2-D splitting exponent mu*(alpha)    */
+                          /* (fids_ifl2d_mu), an explicit mu must lie in           */
+                          /* (alpha, 2)                                            */
 } fids_params;
 
 /* Per-level report. */
@@ -387,6 +400,31 @@ int fids_soe_nodes(double gamma, double delta, double T, double tol, int32_t cap
 
 /* First column of A, eq. (3.16x), into col[0..n-1]; mu = 0 selects 1+alpha/2. */
 int fids_ifl_column(int64_t n, double alpha, double l, double mu, double* col);
+
+/* 2-D operator (dims = 2), for inspection and tests.
+ *
+ * fids_ifl2d_mu: the splitting exponent mu*(alpha) in (alpha, 2) that the
+ *   2-D operator uses when mu = 0: the root of the summed error, over all
+ *   unit lattice cells, of the weighted trapezoidal rule applied to the
+ *   leading term |eta|^{2-mu} of psi (the requirement that, in 1-D, the
+ *   paper's mu = 1 + alpha/2 meets on every interval; Sec. 2.2).  Computed by
+ *   the library once per alpha (partial sums over [-K, K]^2, K = 32, 64, 128,
+ *   extrapolated in K).  EINVAL unless 0 < alpha < 2.
+ * fids_ifl2d_coefficients: a[p + n q], 0 <= p, q < n, the entry of the 2-D
+ *   matrix coupling nodes whose indices differ by (+-p, +-q) (a[0] is the
+ *   diagonal) on (-l, l)^2 with n interior nodes per axis, h = 2l/(n+1):
+ *     A = (c_{2,alpha}/h^alpha) [ D I - sum_{0<|m|_inf<=n-1} W_m |m|^{-mu} S_m ],
+ *     W_m = 1/4 sum of int_C |eta|^{mu-2-alpha} over the unit cells C of
+ *           [-(n+1), n+1]^2 with corner m,
+ *     D   = sum_{0<|m|_inf<=n+1} W_m |m|^{-mu}
+ *           + (8/alpha) (n+1)^{-alpha} int_0^{pi/4} cos^alpha t dt
+ *   (the splitting of (2.11) with psi averaged over each cell's corners and
+ *   omega integrated exactly, and the exact integral beyond the square where
+ *   both neighbours lie outside the domain).  mu = 0 selects mu*(alpha).
+ *   a holds n*n doubles (host).  EINVAL for n < 1, alpha outside (0, 2),
+ *   mu outside (alpha, 2), l <= 0. */
+int fids_ifl2d_mu(double alpha, double* mu);
+int fids_ifl2d_coefficients(int64_t n, double alpha, double l, double mu, double* a);
 
 /* Eigenvalues of Strang's circulant s(A), lam[k] = sum_j c_S[j] cos(2 pi jk/n). */
 int fids_strang_eigs(int64_t n, double alpha, double l, double mu, double* lam);

@@ -154,7 +154,7 @@ def dids_solve(alpha, gamma, n, M, r, kappa, f, phi, l=1.0, T=1.0, mu=None, matr
 
 
 def dids_adjoint(alpha, gamma, n, M, r, kappa, f, phi, dJ_duM, U=None,
-                 l=1.0, T=1.0, mu=None):
+                 l=1.0, T=1.0, mu=None, matrix=None):
     """Exact discrete adjoint of ``dids_solve`` for a loss J(u^M).
 
     Backward over m = M..1 with ubar^m complete on arrival:
@@ -162,11 +162,12 @@ def dids_adjoint(alpha, gamma, n, M, r, kappa, f, phi, dJ_duM, U=None,
       dJ/df^m    = lambda^m
       dJ/dkappa^m_i = -lambda^m_i (A u^m)_i     (summed over m if kappa is [n])
       ubar^0 += g a_1^{(m)} lambda^m,  ubar^k += g (a_{k+1}^{(m)} - a_k^{(m)}) lambda^m
-    and dJ/dphi = ubar^0.  Returns (g_kappa, g_f, g_phi).
+    and dJ/dphi = ubar^0.  Returns (g_kappa, g_f, g_phi).  `matrix` as in
+    ``dids_solve``.
     """
     if U is None:
-        U = dids_solve(alpha, gamma, n, M, r, kappa, f, phi, l, T, mu)
-    A = ifl_matrix(n, alpha, l, mu)
+        U = dids_solve(alpha, gamma, n, M, r, kappa, f, phi, l, T, mu, matrix)
+    A = ifl_matrix(n, alpha, l, mu) if matrix is None else matrix
     g = 1.0 / math.gamma(1.0 - gamma)
     ubar = np.zeros((M + 1, n))
     ubar[M] = dJ_duM

@@ -207,9 +207,9 @@ Layout make_layout(const fids_params& p, const Shapes& sh, size_t sym_budget = k
 
 int shapes_of(const fids_params& p, Shapes& sh, fids::SoeNodes* soe_out) {
   if (fids::validate(p) != FIDS_OK) return FIDS_EINVAL;
-  sh.n = p.n;
+  sh.n = fids::toeplitz_len(p);
   sh.M = p.M;
-  sh.L = fids::embed_length(p.n);
+  sh.L = fids::embed_length(sh.n);
   sh.Nc = sh.L / 2;
   fids::SoeNodes soe;
   const double tau1 = p.T * std::pow(1.0 / double(p.M), p.r);
@@ -370,7 +370,7 @@ int ensure_symbols(fids_problem* h, int64_t m_hi) {
   m_hi = std::min<int64_t>(m_hi, h->sh.M);
   if (h->sym_hi >= m_hi) return FIDS_OK;
   const int a = int(h->sym_hi + 1), cnt = int(m_hi - h->sym_hi);
-  HIPCHK(fids::launch_kbar(h->hp.kappa, int(h->sh.n), a, cnt, h->prm.kappa_time_dependent,
+  HIPCHK(fids::launch_kbar(h->hp.kappa, int(fids::natural_len(h->prm)), a, cnt, h->prm.kappa_time_dependent,
                            at<double>(h->ws, h->lo.kbar), at<double>(h->ws, h->lo.kmax), h->stream));
   for (int m0 = a; m0 <= int(m_hi); m0 += h->lo.chunk) {
     const int c = std::min(h->lo.chunk, int(m_hi) - m0 + 1);
@@ -519,7 +519,11 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   if (st != FIDS_OK) return fail(FIDS_EDEVICE);
   // problem descriptor
   Prob& hp = h->hp;
-  hp.n = int(p->n); hp.M = int(p->M); hp.nexp = t.nexp;
+  hp.n = int(h->sh.n); hp.M = int(p->M); hp.nexp = t.nexp;
+  hp.nn = int(fids::natural_len(*p));
+  hp.nx = p->dims == 2 ? int(p->n) : 0;
+  hp.sx = int(fids::row_stride(*p));
+  hp.lsx = hp.sx > 0 ? ilog2i(hp.sx) : 0;
   hp.solver = p->solver; hp.precision = p->precision; hp.precond = p->precond;
   hp.kappa_td = p->kappa_time_dependent; hp.x0_mode = p->x0_mode; hp.maxit = p->krylov_maxit;
   hp.restart = p->restart; hp.store_states = p->store_states; hp.tol = p->krylov_tol;
@@ -579,7 +583,7 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   h->dstatus = hp.status;
   // symbol job
   SymJob& j = h->hj;
-  j.n = int(p->n); j.L = int(h->sh.L); j.Nc = int(h->sh.Nc); j.M = int(p->M);
+  j.n = int(h->sh.n); j.L = int(h->sh.L); j.Nc = int(h->sh.Nc); j.M = int(p->M);
   fill_plan(j.plc, h->sh.pc, 1, ws, lo, true);
   fill_plan(j.plr, h->sh.ps, 2, ws, lo, false);
   j.beta = hp.beta; j.kbar = at<double>(ws, lo.kbar); j.lam = at<double>(ws, lo.lam);
@@ -630,7 +634,7 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
     hp.nh = nh;
     if (direct && nh > 0) {
       // active rows of a tile hold the natural value pairs below ceil(n / 2)
-      hp.dact = int(((p->n + 1) / 2 + hp.pl.N2 - 1) / hp.pl.N2);
+      hp.dact = int(((h->sh.n + 1) / 2 + hp.pl.N2 - 1) / hp.pl.N2);
       const int nact = hp.pl.ntiles * hp.dact * hp.pl.CT;
       hp.dec = (nact + fids::kThreads - 1) / fids::kThreads;
       hp.djc = std::max(1, std::min(nh / hp.dec, lo.djc_cap));
@@ -951,7 +955,7 @@ int fids_params_default(fids_params* p) {
   p->soe_tol = 1e-10; p->krylov_tol = 1e-12; p->krylov_maxit = 200; p->restart = 20;
   p->solver = FIDS_BICGSTAB; p->precision = FIDS_FP64; p->precond = FIDS_STRANG;
   p->kappa_time_dependent = 1; p->x0_mode = 0; p->store_states = 0; p->wg_count = 0;
-  p->soe_helpers = -1; p->checkpoint_every = 0;
+  p->soe_helpers = -1; p->checkpoint_every = 0; p->dims = 1;
   return FIDS_OK;
 }
 
@@ -1524,6 +1528,21 @@ int fids_ifl_column(int64_t n, double alpha, double l, double mu, double* col) {
   if (!(me > alpha && me <= 2)) return FIDS_EINVAL;
   const auto c = fids::ifl_column(n, alpha, l, me);
   std::copy(c.begin(), c.end(), col);
+  return FIDS_OK;
+}
+
+int fids_ifl2d_mu(double alpha, double* mu) {
+  if (!mu || !(alpha > 0 && alpha < 2)) return FIDS_EINVAL;
+  *mu = fids::ifl2d_mu(alpha);
+  return FIDS_OK;
+}
+
+int fids_ifl2d_coefficients(int64_t n, double alpha, double l, double mu, double* a) {
+  if (!a || n < 1 || n > (int64_t(1) << 11) || !(alpha > 0 && alpha < 2) || !(l > 0)) return FIDS_EINVAL;
+  if (mu != 0 && !(mu > alpha && mu < 2)) return FIDS_EINVAL;
+  const double me = mu > 0 ? mu : fids::ifl2d_mu(alpha);
+  const auto c = fids::ifl2d_coefficients(n, alpha, l, me);
+  std::copy(c.begin(), c.end(), a);
   return FIDS_OK;
 }
 

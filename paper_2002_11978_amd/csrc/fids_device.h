@@ -74,7 +74,9 @@ inline int lds_twiddles(const Plan& pl, int L) {
 
 // Per-problem descriptor, in device memory.
 struct Prob {
-  int n, M, nexp;
+  int n, M, nexp;               // n: order of the Toeplitz matrix the solver applies (padded length in 2-D)
+  int nn;                       // length of the caller's arrays per level: n (1-D) or nx^2 (2-D)
+  int nx, sx, lsx;              // 2-D: nodes per axis, row stride S = 2^lsx (node (i, j) at i + S j); 1-D: 0
   int solver, precision, precond, kappa_td, x0_mode, maxit, restart, store_states;
   double tol;
   int g0, ng;                   // workgroups [g0, g0 + ng) cooperate on this problem
@@ -141,8 +143,8 @@ struct Prob {
   double* ubar[3];              // ubar^m lives in ubar[m % 3]
   double* lam;                  // lambda of the last finished level, tile-major
   double* gk;                   // dJ/dkappa accumulated over levels (time-independent kappa), tile-major
-  double* g_kappa;              // caller's [M][n] dJ/dkappa (time-dependent kappa) or null
-  double* g_f;                  // caller's [M][n] dJ/df or null
+  double* g_kappa;              // caller's [M][nn] dJ/dkappa (time-dependent kappa) or null
+  double* g_f;                  // caller's [M][nn] dJ/df or null
 };
 
 // Bluestein / symbol-precompute descriptor (batched over levels).

@@ -477,11 +477,22 @@ __device__ __forceinline__ void st2nt(double* a, size_t off, double2 v) {
   __builtin_nontemporal_store(v.y, a + off + 1);
 }
 __device__ __forceinline__ void st2(double* a, int off, double2 v) { *reinterpret_cast<double2*>(a + off) = v; }
-__device__ __forceinline__ double2 nat2(const double* a, int i0, int n) {
-  return make_double2(i0 < n ? a[i0] : 0.0, i0 + 1 < n ? a[i0 + 1] : 0.0);
+// Element i of the solver's vectors is an unknown (not padding): i < n and,
+// in 2-D, a node of its row (rows of stride S hold nx nodes).  S is even, so
+// the pair (i0, i0 + 1) of an item never spans two rows: when i0 is padding,
+// so is i0 + 1.
+__device__ __forceinline__ bool valid_at(const Prob& p, int i) {
+  return i < p.n && (p.sx == 0 || (i & (p.sx - 1)) < p.nx);
 }
-__device__ __forceinline__ double2 mask2(double2 v, int i0, int n) {
-  return make_double2(i0 < n ? v.x : 0.0, i0 + 1 < n ? v.y : 0.0);
+// index of unknown i in the caller's (natural) arrays: i, or i + nx j for the node (i, j) at i + S j
+__device__ __forceinline__ int nat_at(const Prob& p, int i) {
+  return p.sx == 0 ? i : (i & (p.sx - 1)) + p.nx * (i >> p.lsx);
+}
+__device__ __forceinline__ double2 nat2(const double* a, int i0, const Prob& p) {
+  return make_double2(valid_at(p, i0) ? a[nat_at(p, i0)] : 0.0, valid_at(p, i0 + 1) ? a[nat_at(p, i0 + 1)] : 0.0);
+}
+__device__ __forceinline__ double2 mask2(double2 v, int i0, const Prob& p) {
+  return make_double2(valid_at(p, i0) ? v.x : 0.0, valid_at(p, i0 + 1) ? v.y : 0.0);
 }
 template <typename R> __device__ __forceinline__ Cx<R> tocx(double2 v) { return mk<R>(R(v.x), R(v.y)); }
 // Input of a P^{-1} application: with the kappa-scaled preconditioner
@@ -653,7 +664,7 @@ __device__ __forceinline__ void direct_helper_step(const Prob& p, int hr, int k)
     if (a >= nact) continue;
     const int tile = a / per_tile, idx = a - tile * per_tile;
     const int i0 = 2 * (pl.N2 * (idx >> logCT) + tile * pl.CT + (idx & (pl.CT - 1)));
-    if (i0 >= p.n) continue;
+    if (!valid_at(p, i0)) continue;
     const int off = tile * blk + 2 * idx;
     const int js = min(j1, k - 1);
     double2 s = make_double2(0.0, 0.0);
@@ -723,7 +734,7 @@ __device__ __forceinline__ int helper_loop(const Prob& p, int hr, int k0, int k1
       const int tile = (2 * q) / blk, lp = (2 * q) % blk;
       const int idx = lp >> 1;
       const int i0 = 2 * (pl.N2 * (idx >> logCT) + tile * pl.CT + (idx & (pl.CT - 1)));
-      if (i0 >= p.n) continue;
+      if (!valid_at(p, i0)) continue;
       const int off = 2 * q;
       const double2 a1 = ld2(um1, off), a2 = ld2(um2, off);
       const double2 d = make_double2(a1.x - a2.x, a1.y - a2.y);
@@ -803,8 +814,8 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
   const double* um1 = p.u[(m - 1) % kRing];
   const double* um2 = p.u[(m - 2 + kRing) % kRing];
   double* x = p.u[m % kRing];              // holds u^{m-kRing} until x0 is stored
-  const double* fm = p.f + size_t(m - 1) * p.n;
-  const double* km = p.kappa + (p.kappa_td ? size_t(m - 1) * p.n : 0);
+  const double* fm = p.f + size_t(m - 1) * p.nn;
+  const double* km = p.kappa + (p.kappa_td ? size_t(m - 1) * p.nn : 0);
   const double* H1m = p.H1 + size_t(m & 1) * p.vlen;
   const bool kscale = kscaled(p);
   const double kb = kscale ? p.kbar[m] : 0.0;
@@ -831,7 +842,7 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
       item(pl, t, idx, i0, sl);
       const int off = t.toff + 2 * idx;
       double2 b = make_double2(0.0, 0.0), x0 = make_double2(0.0, 0.0), r0 = make_double2(0.0, 0.0);
-      if (i0 < p.n) {
+      if (valid_at(p, i0)) {
         const double2 a1 = ld2(um1, off);
         double2 h = make_double2(0.0, 0.0);
         double2 d = make_double2(0.0, 0.0);
@@ -904,12 +915,12 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
             }
           }
         }
-        const double2 fv = nat2(fm, i0, p.n);
-        const double2 kk = nat2(km, i0, p.n);
-        b = direct ? mask2(make_double2(dsum.x + fv.x, dsum.y + fv.y), i0, p.n)
-                   : mask2(make_double2(bm * a1.x - h.x + fv.x, bm * a1.y - h.y + fv.y), i0, p.n);
+        const double2 fv = nat2(fm, i0, p);
+        const double2 kk = nat2(km, i0, p);
+        b = direct ? mask2(make_double2(dsum.x + fv.x, dsum.y + fv.y), i0, p)
+                   : mask2(make_double2(bm * a1.x - h.x + fv.x, bm * a1.y - h.y + fv.y), i0, p);
         if (npts == 2) {
-          x0 = mask2(make_double2(a1.x + rho * d.x, a1.y + rho * d.y), i0, p.n);
+          x0 = mask2(make_double2(a1.x + rho * d.x, a1.y + rho * d.y), i0, p);
         } else if (npts > 0) {
           x0 = make_double2(0.0, 0.0);
           for (int k = 0; k < npts; ++k) {
@@ -917,7 +928,7 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
             x0.x += w[k] * uk.x;
             x0.y += w[k] * uk.y;
           }
-          x0 = mask2(x0, i0, p.n);
+          x0 = mask2(x0, i0, p);
         }
         if (fused) {
           double2 ax = make_double2(0.0, 0.0);
@@ -932,12 +943,12 @@ __device__ __forceinline__ void phase_rhs(const Prob& p, int m, int rank, const 
               ax.y += w[k] * Ak.y;
             }
           }
-          st2(p.AU + size_t(m % kRing) * p.vlen, off, mask2(ax, i0, p.n));
-          r0 = mask2(make_double2(b.x - (bm * x0.x + kk.x * ax.x), b.y - (bm * x0.y + kk.y * ax.y)), i0, p.n);
+          st2(p.AU + size_t(m % kRing) * p.vlen, off, mask2(ax, i0, p));
+          r0 = mask2(make_double2(b.x - (bm * x0.x + kk.x * ax.x), b.y - (bm * x0.y + kk.y * ax.y)), i0, p);
         }
         st2(p.kap, off, kk);
-        acc[2] += (kk.x > 0.0 ? 0.0 : 1.0) + (i0 + 1 < p.n && !(kk.y > 0.0) ? 1.0 : 0.0);
-        if (kscale) st2(p.dsc, off, mask2(make_double2(kb / kk.x, kb / kk.y), i0, p.n));
+        acc[2] += (kk.x > 0.0 ? 0.0 : 1.0) + (valid_at(p, i0 + 1) && !(kk.y > 0.0) ? 1.0 : 0.0);
+        if (kscale) st2(p.dsc, off, mask2(make_double2(kb / kk.x, kb / kk.y), i0, p));
         if (ctl.hist_lo >= 0) st2(p.uhist + size_t(m - 1 - ctl.hist_lo) * p.vlen, off, a1);
       }
       st2(p.vec[VB], off, b);
@@ -989,10 +1000,10 @@ __device__ __forceinline__ void phase_r0(const Prob& p, int m, int rank, const L
       item(pl, t, idx, i0, sl);
       const int off = t.toff + 2 * idx;
       double2 r = make_double2(0.0, 0.0), y = make_double2(0.0, 0.0);
-      if (i0 < p.n) {
-        y = mask2(cscale<double>(L.bd[sl], inv), i0, p.n);
+      if (valid_at(p, i0)) {
+        y = mask2(cscale<double>(L.bd[sl], inv), i0, p);
         const double2 xx = ld2(x, off), kk = ld2(p.kap, off), b = ld2(p.vec[VB], off);
-        r = mask2(make_double2(b.x - (bm * xx.x + kk.x * y.x), b.y - (bm * xx.y + kk.y * y.y)), i0, p.n);
+        r = mask2(make_double2(b.x - (bm * xx.x + kk.x * y.x), b.y - (bm * xx.y + kk.y * y.y)), i0, p);
         acc[1] += xx.x * xx.x + xx.y * xx.y;
       }
       st2(Aum, off, y);
@@ -1021,13 +1032,13 @@ __device__ __forceinline__ void adj_grad_item(const Prob& p, int mg, int i0, int
   const double2 g = make_double2(-lm.x * y.x, -lm.y * y.y);
   if (p.kappa_td) {
     if (p.g_kappa) {
-      double* row = p.g_kappa + size_t(mg - 1) * p.n;
-      row[i0] = g.x;
-      if (i0 + 1 < p.n) row[i0 + 1] = g.y;
+      double* row = p.g_kappa + size_t(mg - 1) * p.nn;
+      row[nat_at(p, i0)] = g.x;
+      if (valid_at(p, i0 + 1)) row[nat_at(p, i0 + 1)] = g.y;
     }
   } else {
     const double2 a = ld2(p.gk, off);
-    st2(p.gk, off, mask2(make_double2(a.x + g.x, a.y + g.y), i0, p.n));
+    st2(p.gk, off, mask2(make_double2(a.x + g.x, a.y + g.y), i0, p));
   }
 }
 
@@ -1056,7 +1067,7 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
     for (int k = 0; k < kRing; ++k) d[k] = (m + 1 + k <= p.M) ? p.xv[m + 1 + k] - p.xv[m] : 1.0;
     extrap_weights(d, npts, w);
   }
-  const double* km = p.kappa + (p.kappa_td ? size_t(m - 1) * p.n : 0);
+  const double* km = p.kappa + (p.kappa_td ? size_t(m - 1) * p.nn : 0);
   const bool kscale = kscaled(p);
   const double kb = kscale ? p.kbar[m] : 0.0;
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
@@ -1068,25 +1079,25 @@ __device__ __forceinline__ void phase_adj_rhs(const Prob& p, int m, int rank, co
       item(pl, t, idx, i0, sl);
       const int off = t.toff + 2 * idx;
       double2 b = make_double2(0.0, 0.0), x0 = make_double2(0.0, 0.0);
-      if (i0 < p.n) {
+      if (valid_at(p, i0)) {
         if (ctl.pending) adj_grad_item(p, m + 1, i0, off, cscale<double>(L.bd[sl], inv));
-        const double2 kk = nat2(km, i0, p.n);
+        const double2 kk = nat2(km, i0, p);
         const double2 u = ld2(ub, off);
-        b = mask2(make_double2(kk.x * u.x, kk.y * u.y), i0, p.n);
+        b = mask2(make_double2(kk.x * u.x, kk.y * u.y), i0, p);
         if (npts == 2) {
           const double2 a1 = ld2(y1, off), a2 = ld2(y2, off);
-          x0 = mask2(make_double2(a1.x + rho * (a1.x - a2.x), a1.y + rho * (a1.y - a2.y)), i0, p.n);
+          x0 = mask2(make_double2(a1.x + rho * (a1.x - a2.x), a1.y + rho * (a1.y - a2.y)), i0, p);
         } else if (npts > 0) {
           for (int k = 0; k < npts; ++k) {
             const double2 yk = ld2(p.u[(m + 1 + k) % kRing], off);   // y^{m+kRing} sits in x
             x0.x += w[k] * yk.x;
             x0.y += w[k] * yk.y;
           }
-          x0 = mask2(x0, i0, p.n);
+          x0 = mask2(x0, i0, p);
         }
         st2(p.kap, off, kk);
-        acc[1] += (kk.x > 0.0 ? 0.0 : 1.0) + (i0 + 1 < p.n && !(kk.y > 0.0) ? 1.0 : 0.0);
-        if (kscale) st2(p.dsc, off, mask2(make_double2(kb / kk.x, kb / kk.y), i0, p.n));
+        acc[1] += (kk.x > 0.0 ? 0.0 : 1.0) + (valid_at(p, i0 + 1) && !(kk.y > 0.0) ? 1.0 : 0.0);
+        if (kscale) st2(p.dsc, off, mask2(make_double2(kb / kk.x, kb / kk.y), i0, p));
       }
       st2(p.vec[VB], off, b);
       st2(x, off, x0);
@@ -1130,7 +1141,7 @@ __device__ __forceinline__ void phase_adj_post(const Prob& p, int m, int rank, c
   double* u1 = p.ubar[(m - 1) % 3];
   double* u2 = p.ubar[(m + 1) % 3];   // (m-2) mod 3
   const double* um = p.uhist + size_t(m - ctl.hist_lo) * p.vlen;
-  double* gf = p.g_f ? p.g_f + size_t(m - 1) * p.n : nullptr;
+  double* gf = p.g_f ? p.g_f + size_t(m - 1) * p.nn : nullptr;
   const int blk = 2 * pl.CT * pl.N1;
   for (int tile = rank; tile < pl.ntiles; tile += p.ng) {
     const TileIdx t = tile_idx(pl, tile);
@@ -1139,13 +1150,13 @@ __device__ __forceinline__ void phase_adj_post(const Prob& p, int m, int rank, c
       item(pl, t, idx, i0, sl);
       const int off = t.toff + 2 * idx;
       double2 uv = make_double2(0.0, 0.0);
-      if (i0 < p.n) {
+      if (valid_at(p, i0)) {
         const double2 yy = ld2(y, off), kk = ld2(p.kap, off);
-        const double2 lm = make_double2(yy.x / kk.x, i0 + 1 < p.n ? yy.y / kk.y : 0.0);
+        const double2 lm = make_double2(yy.x / kk.x, valid_at(p, i0 + 1) ? yy.y / kk.y : 0.0);
         st2(p.lam, off, lm);
         if (gf) {
-          gf[i0] = lm.x;
-          if (i0 + 1 < p.n) gf[i0 + 1] = lm.y;
+          gf[nat_at(p, i0)] = lm.x;
+          if (valid_at(p, i0 + 1)) gf[nat_at(p, i0 + 1)] = lm.y;
         }
         double2 a = ld2(u1, off);
         a.x += bm * lm.x;
@@ -1182,10 +1193,10 @@ __device__ __forceinline__ void phase_adj_post(const Prob& p, int m, int rank, c
           }
           a.x += r.x;
           a.y += r.y;
-          st2(u2, off, mask2(make_double2(-r.x, -r.y), i0, p.n));
+          st2(u2, off, mask2(make_double2(-r.x, -r.y), i0, p));
         }
-        st2(u1, off, mask2(a, i0, p.n));
-        uv = mask2(ld2(um, off), i0, p.n);
+        st2(u1, off, mask2(a, i0, p));
+        uv = mask2(ld2(um, off), i0, p);
       }
       L.bd[sl] = uv;
     }
@@ -1204,7 +1215,7 @@ __device__ __forceinline__ void phase_adj_flush(const Prob& p, int m, int rank, 
     for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
       int i0, sl;
       item(pl, t, idx, i0, sl);
-      if (i0 < p.n) adj_grad_item(p, m, i0, t.toff + 2 * idx, cscale<double>(L.bd[sl], inv));
+      if (valid_at(p, i0)) adj_grad_item(p, m, i0, t.toff + 2 * idx, cscale<double>(L.bd[sl], inv));
     }
   }
 }
@@ -1220,7 +1231,7 @@ __device__ __forceinline__ void bi_C_then_A(const Prob& p, int rank, int dst, co
     for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
       int i0, sl;
       item(pl, t, idx, i0, sl);
-      const double2 z = mask2(cscale<double>(L.bd[sl], inv), i0, p.n);
+      const double2 z = mask2(cscale<double>(L.bd[sl], inv), i0, p);
       st2(p.vec[dst], t.toff + 2 * idx, z);
       L.bd[sl] = z;
     }
@@ -1243,11 +1254,11 @@ __device__ __forceinline__ void bi_C_matvec(const Prob& p, int m, int rank, int 
     for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
       int i0, sl;
       item(pl, t, idx, i0, sl);
-      if (i0 >= p.n) continue;
+      if (!valid_at(p, i0)) continue;
       const int off = t.toff + 2 * idx;
       const double2 y = cscale<double>(L.bd[sl], inv);
       const double2 zz = ld2(z, off), kk = ld2(p.kap, off);
-      const double2 o = mask2(make_double2(bm * zz.x + kk.x * y.x, bm * zz.y + kk.y * y.y), i0, p.n);
+      const double2 o = mask2(make_double2(bm * zz.x + kk.x * y.x, bm * zz.y + kk.y * y.y), i0, p);
       st2(out, off, o);
       const double2 rh = ld2(p.vec[VRH], off);
       if (which == 0) {
@@ -1281,9 +1292,9 @@ __device__ __forceinline__ void bi_s(const Prob& p, int rank, double alpha, cons
       item(pl, t, idx, i0, sl);
       const int off = t.toff + 2 * idx;
       double2 s = make_double2(0.0, 0.0);
-      if (i0 < p.n) {
+      if (valid_at(p, i0)) {
         const double2 r = ld2(p.vec[VR], off), v = ld2(p.vec[VV], off), rh = ld2(p.vec[VRH], off);
-        s = mask2(make_double2(r.x - alpha * v.x, r.y - alpha * v.y), i0, p.n);
+        s = mask2(make_double2(r.x - alpha * v.x, r.y - alpha * v.y), i0, p);
         st2(p.vec[VS], off, s);
         acc[0] += s.x * s.x + s.y * s.y;
         acc[1] += rh.x * s.x + rh.y * s.y;
@@ -1311,17 +1322,17 @@ __device__ __forceinline__ void bi_update(const Prob& p, int m, int rank, double
       item(pl, t, idx, i0, sl);
       const int off = t.toff + 2 * idx;
       double2 pn = make_double2(0.0, 0.0);
-      if (i0 < p.n) {
+      if (valid_at(p, i0)) {
         const double2 ph = ld2(p.vec[VPH], off), sh = ld2(p.vec[VSH], off);
         const double2 s = ld2(p.vec[VS], off), tt = ld2(p.vec[VT], off);
         const double2 po = ld2(p.vec[VP], off), v = ld2(p.vec[VV], off);
         double2 xx = ld2(x, off);
         xx.x += alpha * ph.x + omega * sh.x;
         xx.y += alpha * ph.y + omega * sh.y;
-        st2(x, off, mask2(xx, i0, p.n));
-        const double2 r = mask2(make_double2(s.x - omega * tt.x, s.y - omega * tt.y), i0, p.n);
+        st2(x, off, mask2(xx, i0, p));
+        const double2 r = mask2(make_double2(s.x - omega * tt.x, s.y - omega * tt.y), i0, p);
         st2(p.vec[VR], off, r);
-        pn = mask2(make_double2(r.x + beta * (po.x - omega * v.x), r.y + beta * (po.y - omega * v.y)), i0, p.n);
+        pn = mask2(make_double2(r.x + beta * (po.x - omega * v.x), r.y + beta * (po.y - omega * v.y)), i0, p);
         st2(p.vec[VP], off, pn);
         acc[0] += r.x * r.x + r.y * r.y;
         pn = pc_in(p, off, pn);
@@ -1343,13 +1354,13 @@ __device__ __forceinline__ void bi_half(const Prob& p, int m, int rank, double a
     for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
       int i0, sl;
       item(pl, t, idx, i0, sl);
-      if (i0 >= p.n) continue;
+      if (!valid_at(p, i0)) continue;
       const int off = t.toff + 2 * idx;
       const double2 ph = ld2(p.vec[VPH], off);
       double2 xx = ld2(x, off);
       xx.x += alpha * ph.x;
       xx.y += alpha * ph.y;
-      st2(x, off, mask2(xx, i0, p.n));
+      st2(x, off, mask2(xx, i0, p));
     }
   }
 }
@@ -1522,7 +1533,7 @@ __device__ __forceinline__ void pcg_C_matvec(const Prob& p, int m, int rank, con
         int i0, sl;
         item(pl, t, idx, i0, sl);
         const int off = t.toff + 2 * idx;
-        if (idx < t.total && i0 < p.n) {
+        if (idx < t.total && valid_at(p, i0)) {
           uu[q] = ld2(p.vec[VPH], off);
           kv[q] = ld2(p.kap, off);
           rv[q] = ld2(p.vec[VR], off);
@@ -1533,13 +1544,13 @@ __device__ __forceinline__ void pcg_C_matvec(const Prob& p, int m, int rank, con
         const int idx = base + q * kThreads;
         int i0, sl;
         item(pl, t, idx, i0, sl);
-        if (idx >= t.total || i0 >= p.n) continue;
+        if (idx >= t.total || !valid_at(p, i0)) continue;
         const int off = t.toff + 2 * idx;
         const double2 y = cscale<double>(L.bd[sl], inv);
         const double2 u = uu[q], kk = kv[q], r = rv[q];
-        const double2 w = mask2(make_double2(bm * u.x + kk.x * y.x, bm * u.y + kk.y * y.y), i0, p.n);
+        const double2 w = mask2(make_double2(bm * u.x + kk.x * y.x, bm * u.y + kk.y * y.y), i0, p);
         st2(p.vec[VV], off, w);
-        const double ix = 1.0 / kk.x, iy = i0 + 1 < p.n ? 1.0 / kk.y : 0.0;
+        const double ix = 1.0 / kk.x, iy = valid_at(p, i0 + 1) ? 1.0 / kk.y : 0.0;
         acc[0] += (r.x * u.x) * ix + (r.y * u.y) * iy;
         acc[1] += (w.x * u.x) * ix + (w.y * u.y) * iy;
       }
@@ -1569,7 +1580,7 @@ __device__ __forceinline__ void pcg_update(const Prob& p, int m, int rank, doubl
         int i0, sl;
         item(pl, t, idx, i0, sl);
         const int off = t.toff + 2 * idx;
-        if (idx < t.total && i0 < p.n) {
+        if (idx < t.total && valid_at(p, i0)) {
           uu[q] = ld2(p.vec[VPH], off);
           ww[q] = ld2(p.vec[VV], off);
           if (!first) { po[q] = ld2(p.vec[VP], off); so[q] = ld2(p.vec[VS], off); }
@@ -1586,7 +1597,7 @@ __device__ __forceinline__ void pcg_update(const Prob& p, int m, int rank, doubl
         item(pl, t, idx, i0, sl);
         const int off = t.toff + 2 * idx;
         double2 r = make_double2(0.0, 0.0);
-        if (i0 < p.n) {
+        if (valid_at(p, i0)) {
           double2 pp = uu[q], ss = ww[q];
           if (!first) {
             pp = make_double2(pp.x + beta * po[q].x, pp.y + beta * po[q].y);
@@ -1597,8 +1608,8 @@ __device__ __forceinline__ void pcg_update(const Prob& p, int m, int rank, doubl
           double2 xx = xo[q];
           xx.x += alpha * pp.x;
           xx.y += alpha * pp.y;
-          st2(x, off, mask2(xx, i0, p.n));
-          r = mask2(make_double2(ro[q].x - alpha * ss.x, ro[q].y - alpha * ss.y), i0, p.n);
+          st2(x, off, mask2(xx, i0, p));
+          r = mask2(make_double2(ro[q].x - alpha * ss.x, ro[q].y - alpha * ss.y), i0, p);
           st2(p.vec[VR], off, r);
           acc[0] += r.x * r.x + r.y * r.y;
           r = make_double2(r.x * dd[q].x, r.y * dd[q].y);   // pc_in: PCG always scales by kbar / kappa
@@ -1812,10 +1823,10 @@ __device__ __forceinline__ void gm_P1(const Prob& p, int m, int rank, int j, con
       item(pl, t, idx, i0, sl);
       const int off = t.toff + 2 * idx;
       double2 w = make_double2(0.0, 0.0), sh = make_double2(0.0, 0.0);
-      if (i0 < p.n) {
+      if (valid_at(p, i0)) {
         const double2 y = cscale<double>(L.bd[sl], inv);
         const double2 zz = z_get<RP>(p, j, off), kk = ld2(p.kap, off);
-        w = mask2(make_double2(bm * zz.x + kk.x * y.x, bm * zz.y + kk.y * y.y), i0, p.n);
+        w = mask2(make_double2(bm * zz.x + kk.x * y.x, bm * zz.y + kk.y * y.y), i0, p);
         double2 v = ld2(p.V + size_t(j) * vl, off);
         if (j >= 1) {
           for (int i = 0; i < j; ++i) {
@@ -1831,7 +1842,7 @@ __device__ __forceinline__ void gm_P1(const Prob& p, int m, int rank, int j, con
       }
       st2(p.vec[VV], off, w);
       accw[0] += w.x * w.x + w.y * w.y;
-      lbuf<RP>(L)[sl] = tocx<RP>(i0 < p.n ? pc_in(p, off, sh) : sh);
+      lbuf<RP>(L)[sl] = tocx<RP>(valid_at(p, i0) ? pc_in(p, off, sh) : sh);
     }
     {
       const int sl[1] = {SL_GM + kMaxRestart + 1};
@@ -1845,7 +1856,7 @@ __device__ __forceinline__ void gm_P1(const Prob& p, int m, int rank, int j, con
       for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
         int i0, sl;
         item(pl, t, idx, i0, sl);
-        if (i0 >= p.n) continue;
+        if (!valid_at(p, i0)) continue;
         const int off = t.toff + 2 * idx;
         const double2 w = ld2(p.vec[VV], off);
 #pragma unroll
@@ -1885,7 +1896,7 @@ __device__ __forceinline__ void gm_P3(const Prob& p, int rank, int j, double eta
       item(pl, t, idx, i0, sl);
       const int off = t.toff + 2 * idx;
       double2 z = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
-      if (i0 < p.n) {
+      if (valid_at(p, i0)) {
         const double2 y = fromcx<RP>(lbuf<RP>(L)[sl]);
         z = make_double2(y.x * inv, y.y * inv);
         if (j >= 0) {
@@ -1901,8 +1912,8 @@ __device__ __forceinline__ void gm_P3(const Prob& p, int rank, int j, double eta
           z.x -= h * zi.x; z.y -= h * zi.y;
           v.x -= h * vi.x; v.y -= h * vi.y;
         }
-        z = mask2(make_double2(z.x * ie, z.y * ie), i0, p.n);
-        v = mask2(make_double2(v.x * ie, v.y * ie), i0, p.n);
+        z = mask2(make_double2(z.x * ie, z.y * ie), i0, p);
+        v = mask2(make_double2(v.x * ie, v.y * ie), i0, p);
         accv[0] += v.x * v.x + v.y * v.y;
       }
       L.bd[sl] = z_put<RP>(p, jn, off, z);
@@ -1919,7 +1930,7 @@ __device__ __forceinline__ void gm_P3(const Prob& p, int rank, int j, double eta
       for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
         int i0, sl;
         item(pl, t, idx, i0, sl);
-        if (i0 >= p.n) continue;
+        if (!valid_at(p, i0)) continue;
         const int off = t.toff + 2 * idx;
         const double2 v = ld2(p.V + size_t(jn) * vl, off);
 #pragma unroll
@@ -1949,14 +1960,14 @@ __device__ __forceinline__ void gm_F1(const Prob& p, int m, int rank, int jl, co
       item(pl, t, idx, i0, sl);
       const int off = t.toff + 2 * idx;
       double2 xx = make_double2(0.0, 0.0);
-      if (i0 < p.n) {
+      if (valid_at(p, i0)) {
         xx = ld2(x, off);
         for (int i = 0; i <= jl; ++i) {
           const double2 zi = z_get<RP>(p, i, off);
           xx.x += H.y[i] * zi.x;
           xx.y += H.y[i] * zi.y;
         }
-        xx = mask2(xx, i0, p.n);
+        xx = mask2(xx, i0, p);
         st2(x, off, xx);
       }
       L.bd[sl] = xx;
@@ -1974,7 +1985,7 @@ __device__ __forceinline__ void phase_pc_col64(const Prob& p, int rank, const Ld
     for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
       int i0, sl;
       item(pl, t, idx, i0, sl);
-      L.bd[sl] = i0 < p.n ? pc_in(p, t.toff + 2 * idx, ld2(p.vec[VR], t.toff + 2 * idx)) : make_double2(0.0, 0.0);
+      L.bd[sl] = valid_at(p, i0) ? pc_in(p, t.toff + 2 * idx, ld2(p.vec[VR], t.toff + 2 * idx)) : make_double2(0.0, 0.0);
     }
     tileA_fft_store<double>(pl, tile, L.bd, p.T);
   }
@@ -2304,7 +2315,7 @@ __global__ void __launch_bounds__(kThreads) k_init_state(const Prob* pp) {
     int i0, sl;
     item(pl, t, idx, i0, sl);
     const int off = t.toff + 2 * idx;
-    const double2 v = nat2(p.phi, i0, p.n);
+    const double2 v = nat2(p.phi, i0, p);
     st2(p.u[0], off, v);
     st2(p.u[kRing - 1], off, v);   // u^{-1} := u^0 (never weighted: extrapolation uses levels >= 0)
     if (p.store_states) st2(p.uhist, off, v);
@@ -2316,14 +2327,14 @@ __global__ void __launch_bounds__(kThreads) k_to_natural(const Prob* pp, const d
   const Plan& pl = p.pl;
   const int tile = blockIdx.x;
   src += size_t(blockIdx.y) * p.vlen;
-  dst += size_t(blockIdx.y) * p.n;
+  dst += size_t(blockIdx.y) * p.nn;
   const TileIdx t = tile_idx(pl, tile);
   for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
     int i0, sl;
     item(pl, t, idx, i0, sl);
     const double2 v = ld2(src, t.toff + 2 * idx);
-    if (i0 < p.n) dst[i0] = v.x;
-    if (i0 + 1 < p.n) dst[i0 + 1] = v.y;
+    if (valid_at(p, i0)) dst[nat_at(p, i0)] = v.x;
+    if (valid_at(p, i0 + 1)) dst[nat_at(p, i0 + 1)] = v.y;
   }
 }
 
@@ -2335,7 +2346,7 @@ __global__ void __launch_bounds__(kThreads) k_from_natural(const Prob* pp, const
   for (int idx = threadIdx.x; idx < t.total; idx += kThreads) {
     int i0, sl;
     item(pl, t, idx, i0, sl);
-    st2(dst, t.toff + 2 * idx, nat2(src, i0, p.n));
+    st2(dst, t.toff + 2 * idx, nat2(src, i0, p));
   }
 }
 

@@ -13,11 +13,31 @@ namespace fids {
 
 static const long double kPiL = 3.141592653589793238462643383279502884L;
 
-double mu_effective(const fids_params& p) { return p.mu > 0 ? p.mu : 1.0 + p.alpha / 2; }
+double mu_effective(const fids_params& p) {
+  if (p.mu > 0) return p.mu;
+  return p.dims == 2 ? ifl2d_mu(p.alpha) : 1.0 + p.alpha / 2;
+}
+
+int64_t row_stride(const fids_params& p) {
+  if (p.dims != 2) return 0;
+  int64_t S = 1;
+  while (S < 2 * p.n - 1) S <<= 1;
+  return S;
+}
+
+int64_t toeplitz_len(const fids_params& p) {
+  return p.dims == 2 ? row_stride(p) * (p.n - 1) + p.n : p.n;
+}
+
+int64_t natural_len(const fids_params& p) { return p.dims == 2 ? p.n * p.n : p.n; }
 
 int validate(const fids_params& p) {
-  const double mu = mu_effective(p);
   if (!(p.alpha > 0 && p.alpha < 2)) return FIDS_EINVAL;
+  if (p.dims != 1 && p.dims != 2) return FIDS_EINVAL;
+  if (p.dims == 2 && (p.n < 1 || p.n > (int64_t(1) << 11))) return FIDS_EINVAL;
+  // 2-D: psi has no limit at xi = 0 for mu = 2 (it depends on the direction)
+  if (p.dims == 2 && p.mu != 0 && !(p.mu > p.alpha && p.mu < 2)) return FIDS_EINVAL;
+  const double mu = mu_effective(p);
   if (!(p.gamma > 0 && p.gamma < 1)) return FIDS_EINVAL;
   if (!(mu > p.alpha && mu <= 2)) return FIDS_EINVAL;
   if (!(p.r >= 1) || p.n < 1 || p.M < 1) return FIDS_EINVAL;
@@ -35,7 +55,7 @@ int validate(const fids_params& p) {
   if (p.history != FIDS_HISTORY_SOE && p.history != FIDS_HISTORY_DIRECT) return FIDS_EINVAL;
   // the direct history keeps a triangular table of M (M + 1) / 2 weights
   if (p.history == FIDS_HISTORY_DIRECT && p.M > (int64_t(1) << 16)) return FIDS_EINVAL;
-  if (p.n > (int64_t(1) << 21) || p.M > (int64_t(1) << 24)) return FIDS_EINVAL;
+  if (toeplitz_len(p) > (int64_t(1) << 21) || p.M > (int64_t(1) << 24)) return FIDS_EINVAL;
   return FIDS_OK;
 }
 
@@ -43,6 +63,235 @@ int64_t embed_length(int64_t n) {
   int64_t L = 4;
   while (L < 2 * n) L <<= 1;
   return L;
+}
+
+
+// ---------------------------------------------------------------- 2-D operator
+// The 2-D form of eq. (3.16x) on the square (-l, l)^2 (dims = 2): the
+// splitting of (2.11) with psi(xi) = (2u(x) - u(x+xi) - u(x-xi)) / |xi|^mu and
+// omega = |xi|^{mu-2-alpha}; on every unit cell C of the lattice (xi = h eta)
+// inside |eta|_inf <= N_p, psi is taken as the mean of its corner values and
+// omega is integrated exactly (node m gets W_m = 1/4 sum of int_C omega over
+// its cells), and beyond that square both neighbours lie outside the domain
+// and the integral of 2 u(x) |xi|^{-2-alpha} is exact.
+
+// Gauss-Legendre rule on [-1, 1]: Newton's method on P_k from the Chebyshev
+// guesses, P_k and P_k' by the three-term recurrence.
+static void gauss_legendre(int k, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(k, 0.0);
+  w.assign(k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    long double z = std::cos((long double)kPiL * (i + 0.75L) / (k + 0.5L));
+    long double dp = 1;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1, p1 = z;
+      for (int j = 2; j <= k; ++j) {
+        const long double p2 = ((2 * j - 1) * z * p1 - (j - 1) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = k * (z * p1 - p0) / (z * z - 1);
+      const long double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs((double)dz) < 1e-19) break;
+    }
+    x[i] = double(z);
+    w[i] = double(2 / ((1 - z * z) * dp * dp));
+  }
+}
+
+namespace {
+struct GL {
+  std::vector<double> x8, w8, x12, w12, x40, w40;
+  GL() {
+    gauss_legendre(8, x8, w8);
+    gauss_legendre(12, x12, w12);
+    gauss_legendre(40, x40, w40);
+  }
+};
+const GL& gl() {
+  static const GL g;
+  return g;
+}
+}  // namespace
+
+// int over [a, b] x [c, d] (first quadrant, 0 <= a < b, 0 <= c < d) of
+// (x^2 + y^2)^{beta/2}, -2 < beta < 0.  A cell with a corner at the origin is
+// integrated in polar coordinates (radial part exact, angular part by
+// 40-point Gauss-Legendre on each of the two triangles); cells within 4 of
+// the origin are split into 8 x 8 sub-cells with 12 x 12 points, the others
+// take 8 x 8 points (the singularity is then at least 4 cell widths away).
+static double cell_integral(double a, double b, double c, double d, double beta) {
+  const GL& g = gl();
+  if (a == 0.0 && c == 0.0) {
+    const double nu = beta + 2.0;
+    const double th = std::atan2(d, b);
+    long double s1 = 0, s2 = 0;
+    for (int i = 0; i < 40; ++i) {
+      const double t1 = 0.5 * th * (g.x40[i] + 1.0);
+      s1 += g.w40[i] * std::pow(b / std::cos(t1), nu);
+      const double t2 = th + 0.5 * (0.5 * kPiL - th) * (g.x40[i] + 1.0);
+      s2 += g.w40[i] * std::pow(d / std::sin(t2), nu);
+    }
+    return double((0.5L * th * s1 + 0.5L * (0.5L * kPiL - th) * s2) / nu);
+  }
+  const bool near = std::max(a, c) < 4.0;
+  const int sub = near ? 8 : 1;
+  const std::vector<double>& x = near ? g.x12 : g.x8;
+  const std::vector<double>& w = near ? g.w12 : g.w8;
+  const int k = int(x.size());
+  long double tot = 0;
+  const double hx = (b - a) / sub, hy = (d - c) / sub;
+  for (int i = 0; i < sub; ++i)
+    for (int j = 0; j < sub; ++j) {
+      const double x0 = a + hx * (i + 0.5), y0 = c + hy * (j + 0.5);
+      long double acc = 0;
+      for (int p = 0; p < k; ++p) {
+        const double xx = x0 + 0.5 * hx * x[p];
+        for (int q = 0; q < k; ++q) {
+          const double yy = y0 + 0.5 * hy * x[q];
+          acc += w[p] * w[q] * std::pow(xx * xx + yy * yy, 0.5 * beta);
+        }
+      }
+      tot += acc * 0.25L * hx * hy;
+    }
+  return double(tot);
+}
+
+// First-quadrant cell integrals I[k1 * K + k2] over [k1, k1+1] x [k2, k2+1], k < K.
+static std::vector<double> quadrant_cells(int64_t K, double beta) {
+  std::vector<double> I(size_t(K * K));
+  const int nth = int(std::max<unsigned>(1, std::min<unsigned>(16, std::thread::hardware_concurrency())));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t)
+    pool.emplace_back([&, t] {
+      for (int64_t k1 = t; k1 < K; k1 += nth)
+        for (int64_t k2 = 0; k2 < K; ++k2)
+          I[size_t(k1 * K + k2)] = cell_integral(double(k1), double(k1 + 1), double(k2), double(k2 + 1), beta);
+    });
+  for (auto& th : pool) th.join();
+  return I;
+}
+
+// Error of the rule over [-K, K]^2 for psi = |eta|^{2-mu} (psi(0) = 0):
+// sum over cells of (mean of psi at the corners) int_C omega - int_C |eta|^{-alpha},
+// for K = 32, 64, 128 (partial sums of one pass over [0, 128)^2, times 4).
+static std::array<double, 3> lattice_partials(double mu, double alpha) {
+  constexpr int64_t K = 128;
+  const std::vector<double> Ib = quadrant_cells(K, mu - 2.0 - alpha);
+  const std::vector<double> Ia = quadrant_cells(K, -alpha);
+  auto psi = [&](int64_t i, int64_t j) {
+    return (i == 0 && j == 0) ? 0.0 : std::pow(double(i * i + j * j), 0.5 * (2.0 - mu));
+  };
+  std::array<long double, 3> S{0, 0, 0};
+  for (int64_t k1 = 0; k1 < K; ++k1)
+    for (int64_t k2 = 0; k2 < K; ++k2) {
+      const double avg = 0.25 * (psi(k1, k2) + psi(k1 + 1, k2) + psi(k1, k2 + 1) + psi(k1 + 1, k2 + 1));
+      const long double e = (long double)avg * Ib[size_t(k1 * K + k2)] - Ia[size_t(k1 * K + k2)];
+      const int64_t r = std::max(k1, k2);
+      if (r < 32) S[0] += e;
+      if (r < 64) S[1] += e;
+      S[2] += e;
+    }
+  return {double(4 * S[0]), double(4 * S[1]), double(4 * S[2])};
+}
+
+// The summed error extrapolated in K (its tail is K^{-alpha} (a + b K^{-2}):
+// per-cell errors fall like |eta|^{-2-alpha}).
+static double lattice_error(double mu, double alpha) {
+  const std::array<double, 3> S = lattice_partials(mu, alpha);
+  const double q1 = std::pow(2.0, -alpha), q2 = std::pow(2.0, -alpha - 2.0);
+  const double R0 = (S[1] - q1 * S[0]) / (1.0 - q1), R1 = (S[2] - q1 * S[1]) / (1.0 - q1);
+  return (R1 - q2 * R0) / (1.0 - q2);
+}
+
+double ifl2d_mu(double alpha) {
+  static std::mutex mu_lock;
+  static std::map<double, double> cache;
+  {
+    std::lock_guard<std::mutex> g(mu_lock);
+    auto it = cache.find(alpha);
+    if (it != cache.end()) return it->second;
+  }
+  // the error decreases in mu from +inf (mu -> alpha) to a negative value at
+  // mu = 2: Illinois (modified regula falsi) on [alpha + 1e-6, 2]
+  double a = alpha + 1e-6, b = 2.0;
+  double fa = lattice_error(a, alpha), fb = lattice_error(b, alpha);
+  int side = 0;
+  double m = 0.5 * (a + b);
+  for (int it = 0; it < 100; ++it) {
+    m = (a * fb - b * fa) / (fb - fa);
+    if (!(m > a && m < b)) m = 0.5 * (a + b);
+    const double fm = lattice_error(m, alpha);
+    if ((fm > 0) == (fa > 0)) {
+      a = m;
+      fa = fm;
+      if (side == -1) fb *= 0.5;
+      side = -1;
+    } else {
+      b = m;
+      fb = fm;
+      if (side == 1) fa *= 0.5;
+      side = 1;
+    }
+    if (b - a <= 4e-16 * b || fm == 0.0) break;
+  }
+  std::lock_guard<std::mutex> g(mu_lock);
+  cache[alpha] = m;
+  return m;
+}
+
+std::vector<double> ifl2d_coefficients(int64_t n, double alpha, double l, double mu) {
+  const int64_t Np = n + 1;
+  const double h = 2.0 * l / double(Np);
+  const std::vector<double> Iq = quadrant_cells(Np, mu - 2.0 - alpha);
+  // cell with lower-left corner k (in [-Np, Np)) mirrored into the first quadrant
+  auto cell = [&](int64_t k1, int64_t k2) -> double {
+    if (k1 < -Np || k1 >= Np || k2 < -Np || k2 >= Np) return 0.0;
+    const int64_t s1 = k1 >= 0 ? k1 : -k1 - 1, s2 = k2 >= 0 ? k2 : -k2 - 1;
+    return Iq[size_t(s1 * Np + s2)];
+  };
+  auto W = [&](int64_t m1, int64_t m2) {
+    return 0.25 * (cell(m1, m2) + cell(m1 - 1, m2) + cell(m1, m2 - 1) + cell(m1 - 1, m2 - 1));
+  };
+  // D: every node of the square (by symmetry: the first quadrant with axis
+  // nodes counted twice and the corner node once per mirror image)
+  long double D = 0;
+  for (int64_t m1 = 0; m1 <= Np; ++m1)
+    for (int64_t m2 = 0; m2 <= Np; ++m2) {
+      if (m1 == 0 && m2 == 0) continue;
+      const double w = W(m1, m2) / std::pow(double(m1 * m1 + m2 * m2), 0.5 * mu);
+      const int mult = (m1 == 0 || m2 == 0) ? 2 : 4;
+      D += (long double)mult * w;
+    }
+  {
+    const GL& g = gl();
+    long double e = 0;
+    for (int i = 0; i < 40; ++i) e += g.w40[i] * std::pow(std::cos(kPiL / 8 * (g.x40[i] + 1.0)), alpha);
+    D += 8.0L / alpha * std::pow(double(Np), -alpha) * (kPiL / 8) * e;
+  }
+  const double a2 = alpha * std::pow(2.0, alpha - 1.0) * std::tgamma(1.0 + alpha / 2) /
+                    (double(kPiL) * std::tgamma(1.0 - alpha / 2));
+  const double scale = a2 / std::pow(h, alpha);
+  std::vector<double> a(size_t(n * n));
+  for (int64_t q = 0; q < n; ++q)
+    for (int64_t p = 0; p < n; ++p)
+      a[size_t(p + n * q)] =
+          (p == 0 && q == 0) ? scale * double(D) : -scale * W(p, q) / std::pow(double(p * p + q * q), 0.5 * mu);
+  return a;
+}
+
+std::vector<double> ifl2d_padded_column(int64_t n, double alpha, double l, double mu, int64_t S) {
+  const std::vector<double> a = ifl2d_coefficients(n, alpha, l, mu);
+  std::vector<double> col(size_t(S * (n - 1) + n), 0.0);
+  // node (i, j) sits at i + S j; the entry coupling offsets (p, q) is col[p + S q]
+  // (S >= 2n - 1 keeps the offsets of different q apart)
+  for (int64_t q = 0; q < n; ++q)
+    for (int64_t p = -(n - 1); p < n; ++p) {
+      const int64_t d = p + S * q;
+      if (d >= 0) col[size_t(d)] = a[size_t((p < 0 ? -p : p) + n * q)];
+    }
+  return col;
 }
 
 // ---------------------------------------------------------------- time mesh
@@ -355,9 +604,10 @@ static int soe_build_uncached(double gamma, double delta, double T, double tol, 
 int build_tables(const fids_params& p, HostTables& t) {
   if (validate(p) != FIDS_OK) return FIDS_EINVAL;
   const double mu = mu_effective(p);
-  t.n = p.n;
+  const int64_t nt = toeplitz_len(p);
+  t.n = nt;
   t.M = p.M;
-  t.L = embed_length(p.n);
+  t.L = embed_length(nt);
   t.Nc = t.L / 2;
   t.g = 1.0 / std::tgamma(1.0 - p.gamma);
   t.tau = step_sizes(p.T, p.M, p.r);
@@ -397,18 +647,18 @@ int build_tables(const fids_params& p, HostTables& t) {
     for (int j = 0; j < t.nexp; ++j) c += (long double)t.gw[j] * t.theta[size_t(m) * t.nexp + j];
     t.soec[m] = double(c);
   }
-  t.col = ifl_column(p.n, p.alpha, p.l, mu);
+  t.col = p.dims == 2 ? ifl2d_padded_column(p.n, p.alpha, p.l, mu, row_stride(p)) : ifl_column(p.n, p.alpha, p.l, mu);
   // symbol of the L-circulant whose leading n x n block is A
   {
     std::vector<cplx> e(t.L, cplx(0, 0));
-    for (int64_t j = 0; j < p.n; ++j) e[j] = t.col[j];
-    for (int64_t j = 1; j < p.n; ++j) e[t.L - j] = t.col[j];
+    for (int64_t j = 0; j < nt; ++j) e[j] = t.col[j];
+    for (int64_t j = 1; j < nt; ++j) e[t.L - j] = t.col[j];
     host_fft(e, -1);
     t.ahat.resize(t.Nc + 1);
     for (int64_t k = 0; k <= t.Nc; ++k) t.ahat[k] = e[k].real();
   }
   t.lam = strang_eigs(t.col);
-  t.chirp = make_chirp(p.n);
+  t.chirp = make_chirp(nt);
   t.chirp_hat = embed_conj_chirp_hat(t.chirp, t.L);
   return FIDS_OK;
 }

@@ -46,10 +46,25 @@ struct HostTables {
 // Parameter checks of fids_init_problem; returns FIDS_OK or FIDS_EINVAL.
 int validate(const fids_params& p);
 
-// Effective mu (0 selects 1 + alpha/2).
+// Effective mu (0 selects 1 + alpha/2, or mu*(alpha) for dims = 2).
 double mu_effective(const fids_params& p);
 
+// Layout of the unknowns: dims = 1, n of them; dims = 2, node (i, j) of the
+// n x n grid at i + S j with the row stride S (the smallest power of two
+// >= 2n - 1), so that the block-Toeplitz matrix acts as one symmetric
+// Toeplitz matrix of order S (n - 1) + n on the padded vector.
+int64_t row_stride(const fids_params& p);    // S (0 for dims = 1)
+int64_t toeplitz_len(const fids_params& p);  // order of that Toeplitz matrix
+int64_t natural_len(const fids_params& p);   // n or n^2: length of the caller's arrays
+
 int64_t embed_length(int64_t n);
+
+// 2-D operator (dims = 2): the splitting exponent mu*(alpha), the
+// coefficients a[p + n q] of the block-Toeplitz matrix, and the first column
+// of the padded Toeplitz matrix with row stride S.
+double ifl2d_mu(double alpha);
+std::vector<double> ifl2d_coefficients(int64_t n, double alpha, double l, double mu);
+std::vector<double> ifl2d_padded_column(int64_t n, double alpha, double l, double mu, int64_t S);
 
 // The pieces, exposed for the introspection entry points.
 std::vector<double> ifl_column(int64_t n, double alpha, double l, double mu);

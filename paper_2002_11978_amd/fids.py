@@ -35,7 +35,25 @@ class Params(ctypes.Structure):
         ("precond", ctypes.c_int32), ("kappa_time_dependent", ctypes.c_int32),
         ("x0_mode", ctypes.c_int32), ("store_states", ctypes.c_int32), ("wg_count", ctypes.c_int32),
         ("soe_helpers", ctypes.c_int32), ("history", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
+        ("dims", ctypes.c_int32),
     ]
+
+
+def natural_len(params) -> int:
+    """Unknowns per level: n, or n * n for dims = 2 (the caller's array length)."""
+    return int(params.n) ** 2 if int(params.dims) == 2 else int(params.n)
+
+
+def toeplitz_len(params) -> int:
+    """Order of the Toeplitz matrix the library applies: n, or S (n - 1) + n
+    for dims = 2 (rows of stride S, the smallest power of two >= 2n - 1)."""
+    n = int(params.n)
+    if int(params.dims) != 2:
+        return n
+    S = 1
+    while S < 2 * n - 1:
+        S *= 2
+    return S * (n - 1) + n
 
 
 class StepInfo(ctypes.Structure):
@@ -96,6 +114,9 @@ _SIGS = {
     "fids_soe_nodes": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_int32, _D, _D, ctypes.POINTER(ctypes.c_int32)]),
     "fids_ifl_column": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]),
+    "fids_ifl2d_mu": (ctypes.c_int, [ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+    "fids_ifl2d_coefficients": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                               _D]),
     "fids_strang_eigs": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]),
     "fids_level_coefficients": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                                ctypes.c_double, _D]),
@@ -183,6 +204,20 @@ def ifl_column(n, alpha, l=1.0, mu=0.0):
     return out
 
 
+def ifl2d_mu(alpha):
+    out = ctypes.c_double(0.0)
+    _check(lib().fids_ifl2d_mu(alpha, ctypes.byref(out)), "fids_ifl2d_mu")
+    return out.value
+
+
+def ifl2d_coefficients(n, alpha, l=1.0, mu=0.0):
+    """a[p, q] (numpy, n x n) of the 2-D matrix, as the library builds it."""
+    import numpy as np
+    out = np.zeros(n * n)
+    _check(lib().fids_ifl2d_coefficients(n, alpha, l, mu, _dptr(out)), "fids_ifl2d_coefficients")
+    return out.reshape(n, n).T.copy()      # stored a[p + n q]: rows q -> transpose to [p, q]
+
+
 def strang_eigs(n, alpha, l=1.0, mu=0.0):
     import numpy as np
     out = np.zeros(n)
@@ -228,7 +263,7 @@ def solve_static(params: Params, kappa, f, phi, stream=None):
         if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
             raise ValueError(f"{name} must be a contiguous float64 device tensor")
     s = stream if stream is not None else torch.cuda.current_stream(kappa.device)
-    uT = torch.empty(int(params.n), dtype=torch.float64, device=kappa.device)
+    uT = torch.empty(natural_len(params), dtype=torch.float64, device=kappa.device)
     infos = (StepInfo * int(params.M))()
     _check(lib().fids_solve_static(ctypes.byref(params), _ptr(kappa), _ptr(f), _ptr(phi), _ptr(uT), infos,
                                    ctypes.c_void_p(s.cuda_stream)), "fids_solve_static")
@@ -276,7 +311,8 @@ class Problem:
 
     @property
     def n(self):
-        return int(self.params.n)
+        """Unknowns per level (n, or n * n for dims = 2)."""
+        return natural_len(self.params)
 
     @property
     def M(self):
@@ -349,11 +385,12 @@ class Problem:
     def precond_symbol(self, m):
         """(q, qhat) of level m's Strang preconditioner as built on the device (host arrays)."""
         import numpy as np
+        nt = toeplitz_len(self.params)
         L = 1
-        while L < 2 * self.n:
+        while L < 2 * nt:
             L *= 2
         L = max(L, 4)
-        q = np.zeros(self.n)
+        q = np.zeros(nt)
         qhat = np.zeros(L // 2 + 1)
         _check(lib().fids_precond_symbol(self.h, m, _dptr(q), _dptr(qhat)), "fids_precond_symbol")
         return q, qhat
@@ -393,7 +430,7 @@ class Batch:
         self.kappas, self.fs, self.phis = list(kappas), list(fs), list(phis)
         self.device = kappas[0].device
         self.M = int(params[0].M)
-        self.ns = [int(p.n) for p in params]
+        self.ns = [natural_len(p) for p in params]
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         nb = ctypes.c_size_t(0)
         _check(lib().fids_batch_workspace_size(self.params, count, ctypes.byref(nb)), "fids_batch_workspace_size")

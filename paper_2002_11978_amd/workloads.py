@@ -84,6 +84,7 @@ class Problem:
     exact: np.ndarray | None = None
     kappa_time_dependent: bool = True
     name: str = ""
+    dims: int = 1              # 2: n nodes per axis of (-l, l)^2, fields flattened x-fastest (i + n j)
 
     @property
     def mu_eff(self) -> float:
@@ -178,6 +179,34 @@ def seeded(alpha, gamma, n, M, r=None, kappa_seed=1, f_seed=2,
     phi = np.maximum(1.0 - x * x, 0.0) ** (alpha / 2)
     return Problem(alpha, gamma, n, M, r, 1.0, 1.0, 0.0, np.ascontiguousarray(kap),
                    np.ascontiguousarray(f), phi, None, time_dependent, name)
+
+
+def seeded2d(alpha, gamma, n, M, r=None, kappa_seed=1, f_seed=2,
+             time_dependent=True, name="seeded2d") -> Problem:
+    """Seeded smooth fields on the square (-1, 1)^2, n nodes per axis
+    (dims = 2), flattened x-fastest (node (i, j) at i + n j):
+    kappa(x, y, t) = (k_a(x, t) + k_b(y, t)) / 2 from two seeded 1-D kappa
+    fields (>= 0.1), f(x, y, t) = s_a(x, t) g(y) + g(x) s_b(y, t) with two
+    seeded 1-D sources and g(z) = sin(pi (z + 1)/2), and the non-smooth
+    initial datum phi = (1 - x^2 - y^2)_+^{alpha/2}."""
+    r = default_grading(gamma) if r is None else r
+    x = node_coords(n, 1.0)
+    t = time_levels(1.0, M, r)[1:]
+    ka = seeded_kappa(x, t, kappa_seed, time_dependent)
+    kb = seeded_kappa(x, t, kappa_seed + 7919, time_dependent)
+    if time_dependent:
+        kap = 0.5 * (ka[:, None, :] + kb[:, :, None])            # [M, y, x]
+        kap = kap.reshape(M, n * n)
+    else:
+        kap = (0.5 * (ka[None, :] + kb[:, None])).reshape(n * n)
+    g = np.sin(np.pi * (x + 1.0) / 2.0)
+    sa = seeded_source(x, t, f_seed)
+    sb = seeded_source(x, t, f_seed + 7919)
+    f = (sa[:, None, :] * g[None, :, None] + g[None, None, :] * sb[:, :, None]).reshape(M, n * n)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    phi = (np.maximum(1.0 - X * X - Y * Y, 0.0) ** (alpha / 2)).reshape(n * n)
+    return Problem(alpha, gamma, n, M, r, 1.0, 1.0, 0.0, np.ascontiguousarray(kap),
+                   np.ascontiguousarray(f), phi, None, time_dependent, name, dims=2)
 
 
 def batch_shapes(count=256, seed0=1000, n_lo=511, n_hi=16383):

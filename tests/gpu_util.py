@@ -21,7 +21,7 @@ def gpu_solve(pb, return_all=True, **kw):
     td = int(pb.kappa.ndim == 2)
     params = fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=pb.M, r=pb.r, mu=pb.mu,
                                  l=pb.l, T=pb.T, kappa_time_dependent=td,
-                                 store_states=int(return_all))
+                                 store_states=int(return_all), dims=getattr(pb, "dims", 1))
     for k, v in kw.items():
         setattr(params, k, v)
     say(f"[gpu] n={pb.n} M={pb.M} alpha={pb.alpha} gamma={pb.gamma} r={pb.r:.4g} "

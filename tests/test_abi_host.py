@@ -201,3 +201,42 @@ def test_direct_weights_against_extended_precision(M, r, gamma, m):
         ak = float(g * a(max(k, 1)))
         assert abs(w[k] - float(exact)) <= 1e-9 * abs(float(exact)) + 1e-14 * ak, (k, w[k], float(exact))
     assert abs(float(np.sum(w)) - float(g * a(m))) <= 1e-12 * scale + 1e-12
+
+
+# ---------------------------------------------------------------- 2-D operator
+@pytest.mark.parametrize("alpha", [0.1, 0.7, 1.3, 1.9])
+def test_ifl2d_mu_matches_oracle(alpha):
+    """The library's splitting exponent mu*(alpha) (its own cell quadrature and
+    root finding) against the oracle's (closed-form cell integrals)."""
+    assert fids.ifl2d_mu(alpha) == pytest.approx(oracle.mu_star(alpha), abs=1e-9)
+
+
+@pytest.mark.parametrize("n", [1, 2, 15, 64])
+@pytest.mark.parametrize("alpha", [0.4, 1.5, 1.95])
+def test_ifl2d_coefficients_match_oracle(n, alpha):
+    """Block-Toeplitz coefficients a[p, q] of the 2-D matrix at the same mu:
+    the two sides integrate the cells differently (Gauss-Legendre against
+    hypergeometric closed forms), so agreement is to quadrature accuracy."""
+    mu = oracle.mu_star(alpha)
+    got = fids.ifl2d_coefficients(n, alpha, 1.3, mu)
+    ref = oracle.ifl2d_coefficients(n, alpha, 1.3, mu)
+    assert np.max(np.abs(got - ref)) <= 1e-11 * abs(ref[0, 0])
+    # default mu: the library's own mu*, within its root's tolerance
+    d = fids.ifl2d_coefficients(n, alpha, 1.3, 0.0)
+    assert np.max(np.abs(d - ref)) <= 1e-8 * abs(ref[0, 0])
+
+
+@pytest.mark.parametrize("field,value", [("dims", 0), ("dims", 3), ("mu", 2.0), ("mu", 0.5), ("n", 2049)])
+def test_invalid_2d_parameters_rejected(field, value):
+    kw = dict(dims=2, n=31, alpha=1.5)
+    kw[field] = value
+    p = fids.default_params(**kw)
+    sz = ctypes.c_size_t(0)
+    assert fids.lib().fids_workspace_size(ctypes.byref(p), ctypes.byref(sz)) == fids.FIDS_EINVAL
+
+
+def test_2d_layout_lengths():
+    p = fids.default_params(dims=2, n=255)
+    assert fids.natural_len(p) == 255 * 255
+    assert fids.toeplitz_len(p) == 512 * 254 + 255
+    assert fids.workspace_size(p) > fids.workspace_size(fids.default_params(n=255))
