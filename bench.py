@@ -80,6 +80,7 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=4095)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2-D extension's leg")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--table11", action="store_true",
                     help="Table 11 rows (Example 2) on the GPU: fast/direct history, with/without preconditioner")
@@ -194,6 +195,67 @@ def adjoint_leg(tol):
               f"ratio {best[1] / best[0]:.2f}", file=sys.stderr, flush=True)
         prob.close()
     out["adj_over_fwd"] = out["checkpoint_32"]["adj_over_fwd"]
+    return out
+
+
+def leg_2d(tol, n=255, M=256):
+    """The 2-D extension (dims = 2) on (-1, 1)^2 with n nodes per axis: full
+    solves of M levels (symbols built inside) and one kernel-only launch of
+    the level kernel over all levels, in the headline's PCG form and FGMRES.
+    Algorithmic bytes use the n^2 unknowns (the padded rows the library
+    streams hold about twice as many slots, see `padded_len`)."""
+    import torch
+
+    from paper_2002_11978_amd import fids
+    from paper_2002_11978_amd import workloads as W
+    pb = W.seeded2d(1.5, 0.4, n, M, r=4.0, kappa_seed=61, f_seed=62)
+    dev = torch.device("cuda:0")
+    k, f, phi = (torch.from_numpy(a).to(dev) for a in (pb.kappa, pb.f, pb.phi))
+    out = {"workload": f"2-D square (-1,1)^2, n={n} nodes per axis ({n * n} unknowns), M={M}, alpha=1.5, "
+                       f"gamma=0.4, r=4, seeded kappa(x,y,t), f(x,y,t), phi=(1-|x|^2)_+^(alpha/2)"}
+    for form in ("headline", "fgmres"):
+        cfg = {kk: v for kk, v in FORMS[form].items() if kk != "label"}
+        prm = fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=n, M=M, r=pb.r, soe_tol=1e-10,
+                                  krylov_tol=tol, krylov_maxit=500, kappa_time_dependent=1, dims=2, **cfg)
+        prob = fids.Problem(prm, k, f, phi)
+        infos = (fids.StepInfo * M)()
+        best = None
+        for rep in range(3):
+            prob.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = prob.solve_all_raw(None, None, infos)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if st != 0:
+                raise fids.FidsError(st, "fids_solve_all")
+            if rep > 0 and (best is None or dt < best):
+                best = dt
+        prob.reset()
+        prob.prepare()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(prob.stream)
+        st = prob.solve_all_raw(None, None, infos)
+        e1.record(prob.stream)
+        torch.cuda.synchronize()
+        kern = e0.elapsed_time(e1)
+        its = np.array([infos[i].iters for i in range(M)])
+        mvs = np.array([infos[i].matvecs for i in range(M)])
+        rr = max(infos[i].relres for i in range(M))
+        nexp = len(fids.soe_nodes(pb.gamma, pb.T * (1.0 / M) ** pb.r, pb.T, 1e-10)[0])   # delta = tau_1
+        byts = sum(level_bytes(form, n * n, nexp, int(its[i]), int(mvs[i])) for i in range(M))
+        ach = byts / (kern * 1e-3) / 1e9
+        out[form] = {"form": FORMS[form]["label"], "levels_per_s": M / best, "solve_ms": best * 1e3,
+                     "kernel_ms": kern, "avg_iters": float(its.mean()), "relres_max": rr,
+                     "padded_len": fids.toeplitz_len(prm),
+                     "roofline": {"bound": "hbm", "achieved": ach, "peak": 8000.0, "unit": "GB/s",
+                                  "frac": ach / 8000.0, "bytes_per_launch": byts, "traffic": None}}
+        print(f"[bench] 2-D {form}: n={n}^2 M={M}: {M / best:.0f} levels/s ({best * 1e3:.1f} ms per solve), "
+              f"kernel {kern:.1f} ms, its {its.mean():.2f}, relres_max {rr:.2e}, {ach:.0f} GB/s algorithmic",
+              file=sys.stderr, flush=True)
+        prob.close()
     return out
 
 
@@ -644,6 +706,8 @@ def main():
         out["adj_fwd_ratio"] = out["adjoint"]["adj_over_fwd"]
     if not args.no_batch:
         out["batch"] = batch_leg(args.tol, args.batch_count)
+    if not args.no_2d:
+        out["two_d"] = leg_2d(args.tol)
     if args.table11:
         out["table11"] = table11_leg()
     if not args.no_cpu:

@@ -524,6 +524,8 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
   hp.nx = p->dims == 2 ? int(p->n) : 0;
   hp.sx = int(fids::row_stride(*p));
   hp.lsx = hp.sx > 0 ? ilog2i(hp.sx) : 0;
+  hp.vmask = hp.sx > 0 ? hp.sx - 1 : 0;
+  hp.vlim = hp.sx > 0 ? hp.nx : 1;
   hp.solver = p->solver; hp.precision = p->precision; hp.precond = p->precond;
   hp.kappa_td = p->kappa_time_dependent; hp.x0_mode = p->x0_mode; hp.maxit = p->krylov_maxit;
   hp.restart = p->restart; hp.store_states = p->store_states; hp.tol = p->krylov_tol;

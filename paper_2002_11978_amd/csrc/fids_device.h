@@ -77,6 +77,7 @@ struct Prob {
   int n, M, nexp;               // n: order of the Toeplitz matrix the solver applies (padded length in 2-D)
   int nn;                       // length of the caller's arrays per level: n (1-D) or nx^2 (2-D)
   int nx, sx, lsx;              // 2-D: nodes per axis, row stride S = 2^lsx (node (i, j) at i + S j); 1-D: 0
+  int vmask, vlim;              // element i is an unknown iff i < n and (i & vmask) < vlim (1-D: 0, 1)
   int solver, precision, precond, kappa_td, x0_mode, maxit, restart, store_states;
   double tol;
   int g0, ng;                   // workgroups [g0, g0 + ng) cooperate on this problem

@@ -481,12 +481,13 @@ __device__ __forceinline__ void st2(double* a, int off, double2 v) { *reinterpre
 // in 2-D, a node of its row (rows of stride S hold nx nodes).  S is even, so
 // the pair (i0, i0 + 1) of an item never spans two rows: when i0 is padding,
 // so is i0 + 1.
+// Branch-free: 1-D has vmask 0 and vlim 1, so the row test always holds.
 __device__ __forceinline__ bool valid_at(const Prob& p, int i) {
-  return i < p.n && (p.sx == 0 || (i & (p.sx - 1)) < p.nx);
+  return (i < p.n) & ((i & p.vmask) < p.vlim);
 }
 // index of unknown i in the caller's (natural) arrays: i, or i + nx j for the node (i, j) at i + S j
 __device__ __forceinline__ int nat_at(const Prob& p, int i) {
-  return p.sx == 0 ? i : (i & (p.sx - 1)) + p.nx * (i >> p.lsx);
+  return p.vmask == 0 ? i : (i & p.vmask) + p.nx * (i >> p.lsx);
 }
 __device__ __forceinline__ double2 nat2(const double* a, int i0, const Prob& p) {
   return make_double2(valid_at(p, i0) ? a[nat_at(p, i0)] : 0.0, valid_at(p, i0 + 1) ? a[nat_at(p, i0 + 1)] : 0.0);
