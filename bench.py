@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--table11", action="store_true",
                     help="Table 11 rows (Example 2) on the GPU: fast/direct history, with/without preconditioner")
-    ap.add_argument("--profile-pass", nargs="?", const="headline", choices=["headline", "batch"],
+    ap.add_argument("--profile-pass", nargs="?", const="headline", choices=["headline", "batch", "2d"],
                     help="a 256 MiB device copy, then one launch of the level kernel over all levels: the "
                          "headline form (default) or the 256-problem batch in its PCG form (for counters)")
     return ap.parse_args()
@@ -198,7 +198,7 @@ def adjoint_leg(tol):
     return out
 
 
-def leg_2d(tol, n=255, M=256):
+def leg_2d(tol, n=255, M=256, forms=("headline", "fgmres"), kernel_only=False):
     """The 2-D extension (dims = 2) on (-1, 1)^2 with n nodes per axis: full
     solves of M levels (symbols built inside) and one kernel-only launch of
     the level kernel over all levels, in the headline's PCG form and FGMRES.
@@ -213,14 +213,14 @@ def leg_2d(tol, n=255, M=256):
     k, f, phi = (torch.from_numpy(a).to(dev) for a in (pb.kappa, pb.f, pb.phi))
     out = {"workload": f"2-D square (-1,1)^2, n={n} nodes per axis ({n * n} unknowns), M={M}, alpha=1.5, "
                        f"gamma=0.4, r=4, seeded kappa(x,y,t), f(x,y,t), phi=(1-|x|^2)_+^(alpha/2)"}
-    for form in ("headline", "fgmres"):
+    for form in forms:
         cfg = {kk: v for kk, v in FORMS[form].items() if kk != "label"}
         prm = fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=n, M=M, r=pb.r, soe_tol=1e-10,
                                   krylov_tol=tol, krylov_maxit=500, kappa_time_dependent=1, dims=2, **cfg)
         prob = fids.Problem(prm, k, f, phi)
         infos = (fids.StepInfo * M)()
         best = None
-        for rep in range(3):
+        for rep in range(0 if kernel_only else 3):
             prob.reset()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -241,6 +241,11 @@ def leg_2d(tol, n=255, M=256):
         e1.record(prob.stream)
         torch.cuda.synchronize()
         kern = e0.elapsed_time(e1)
+        if kernel_only:                 # the counter pass: one launch, handle closed
+            prob.close()
+            if st != 0:
+                raise fids.FidsError(st, "fids_solve_all")
+            return kern
         its = np.array([infos[i].iters for i in range(M)])
         mvs = np.array([infos[i].matvecs for i in range(M)])
         rr = max(infos[i].relres for i in range(M))
@@ -252,6 +257,11 @@ def leg_2d(tol, n=255, M=256):
                      "padded_len": fids.toeplitz_len(prm),
                      "roofline": {"bound": "hbm", "achieved": ach, "peak": 8000.0, "unit": "GB/s",
                                   "frac": ach / 8000.0, "bytes_per_launch": byts, "traffic": None}}
+        tr = measured_traffic(n, M, TRAFFIC_2D_FILE, "2-D " + FORMS[form]["label"]) if form == "headline" else None
+        if tr is not None:
+            out[form]["roofline"]["traffic"] = tr["traffic_bytes_per_launch"]
+            out[form]["roofline"]["traffic_source"] = os.path.relpath(TRAFFIC_2D_FILE,
+                                                                    os.path.dirname(os.path.abspath(__file__)))
         print(f"[bench] 2-D {form}: n={n}^2 M={M}: {M / best:.0f} levels/s ({best * 1e3:.1f} ms per solve), "
               f"kernel {kern:.1f} ms, its {its.mean():.2f}, relres_max {rr:.2e}, {ach:.0f} GB/s algorithmic",
               file=sys.stderr, flush=True)
@@ -523,6 +533,8 @@ TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profile
                             "k_levels_n65535_M2048_traffic.json")
 BATCH_TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                                   "k_levels_batch256_M256_traffic.json")
+TRAFFIC_2D_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "k_levels_2d_n255_M256_traffic.json")
 KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2002_11978_amd", "csrc",
                           "fids_kernels.hip")
 
@@ -567,6 +579,12 @@ def profile_pass(args):
         profile_batch(args, dev)
         del src, dst
         torch.cuda.synchronize()
+        return
+    if args.profile_pass == "2d":
+        ms = leg_2d(args.tol, forms=("headline",), kernel_only=True)
+        del src, dst
+        torch.cuda.synchronize()
+        print(f"[profile-pass] copy 256 MiB, 2-D k_levels {ms:.1f} ms", file=sys.stderr, flush=True)
         return
     pb = workload(args.n, args.M)
     pb.kappa_d, pb.f_d, pb.phi_d = (torch.from_numpy(a).to(dev) for a in (pb.kappa, pb.f, pb.phi))
