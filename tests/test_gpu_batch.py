@@ -25,7 +25,7 @@ MIXED = dict(solver=1, precision=1, x0_mode=1)
 
 def _params(pb, **kw):
     p = fids.default_params(alpha=pb.alpha, gamma=pb.gamma, n=pb.n, M=pb.M, r=pb.r, mu=pb.mu,
-                            kappa_time_dependent=int(pb.kappa.ndim == 2))
+                            kappa_time_dependent=int(pb.kappa.ndim == 2), dims=getattr(pb, "dims", 1))
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -253,4 +253,35 @@ def test_batch_tune_class_with_uneven_soe_sizes():
     assert st == [0] * len(pbs)
     for a, o in zip(ref, outs):
         assert rel_maxnorm(o.cpu().numpy(), a) <= 1e-9
+    b.close()
+
+
+@pytest.mark.parametrize("kw", [dict(solver=2, precision=0, x0_mode=3), MIXED], ids=["pcg-fp64", "fgmres-mixed"])
+def test_batch_with_2d_members(kw):
+    """1-D and 2-D members (dims = 2, the padded-row layout) in one persistent
+    launch: each equals its solo run bit for bit, and the 2-D members match
+    the oracle's 2-D direct scheme."""
+    M = 8
+    pbs = [W.seeded2d(1.5, 0.5, 15, M, kappa_seed=400, f_seed=401),
+           W.seeded(1.3, 0.6, 300, M, kappa_seed=402, f_seed=403),
+           W.seeded2d(1.1, 0.3, 31, M, kappa_seed=404, f_seed=405),
+           W.seeded2d(1.8, 0.7, 63, M, kappa_seed=406, f_seed=407)]
+    for pb in pbs:
+        if pb.dims == 2:
+            pb.mu = oracle.mu_star(pb.alpha)
+    b = _batch(pbs, **kw)
+    groups = b.groups()
+    outs, reps = b.solve_all()
+    gate = 1e-7 if kw.get("precision") == 1 else 1e-8
+    for i, pb in enumerate(pbs):
+        u = outs[i].cpu().numpy()
+        solo, solo_reps = _solo(pb, wg=groups[i], **kw)
+        assert np.array_equal(u, solo), f"member {i} differs from its solo run"
+        if pb.dims == 2:
+            R = oracle.dids2d_solve(pb.alpha, pb.gamma, pb.n, M, pb.r, pb.kappa, pb.f, pb.phi, mu=pb.mu)
+        else:
+            R = oracle.dids_solve(pb.alpha, pb.gamma, pb.n, M, pb.r, pb.kappa, pb.f, pb.phi)
+        err = rel_maxnorm(u, R[-1])
+        say(f"  member {i} dims={pb.dims} n={pb.n} group {groups[i]}: rel err vs oracle {err:.3e}")
+        assert err <= gate
     b.close()
