@@ -82,7 +82,7 @@ int env_int(const char* name, int dflt) {
 
 // Workspace layout of one problem.  Offsets are bytes from ws_d.
 struct Layout {
-  size_t prob, job, abort_, status, bar, info, part;
+  size_t prob, job, abort_, symflag, status, bar, info, part;
   size_t beta, theta, decay, gw, ahat, lam, chirp, chirp_hat, kbar, kmax, xv;
   size_t tw1r, tw1rf, tw2r, tw2rf, tw1c, tw1cf, tw2c, tw2cf, twlo, twlof, twhi, twhif;
   size_t qhat, qhatf;
@@ -125,6 +125,7 @@ Layout make_layout(const fids_params& p, const Shapes& sh, size_t sym_budget = k
   lo.prob = take(sizeof(Prob));
   lo.job = take(sizeof(SymJob));
   lo.abort_ = take(sizeof(int));
+  lo.symflag = take(sizeof(unsigned));
   lo.status = take(4 * sizeof(int));
   lo.bar = take(fids::kBarBytes);
   lo.info = take(M * sizeof(fids_step_info));
@@ -279,10 +280,20 @@ struct fids_problem {
   bool poisoned = false;     // a level failed: the state is only valid after fids_reset
   size_t lds = 0;
   unsigned long long timeout_ticks = 0;
+  // symbols built on a stream of their own while the level kernel runs
+  // (null: built on `stream` before the launch)
+  hipStream_t sstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  unsigned* symflag = nullptr;
   // host copies kept alive for asynchronous uploads
   std::vector<std::vector<double2>> keep2;
   std::vector<std::vector<float2>> keepf;
   std::vector<double> keepd;     // direct-history weights
+  ~fids_problem() {
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (sstream) (void)hipStreamDestroy(sstream);
+  }
 };
 
 struct fids_batch {
@@ -365,29 +376,37 @@ int fit_lds(Prob& hp, size_t cap) {
 }
 
 // Builds kbar_m, kmax_m and the per-level preconditioner symbols of levels
-// sym_hi+1..m_hi (those of earlier levels are current).
-int ensure_symbols(fids_problem* h, int64_t m_hi) {
-  m_hi = std::min<int64_t>(m_hi, h->sh.M);
-  if (h->sym_hi >= m_hi) return FIDS_OK;
+// sym_hi+1..m_hi (those of earlier levels are current) on stream s, raising
+// the problem's symbol flag after each chunk of levels when it has one.
+int build_symbols(fids_problem* h, int64_t m_hi, hipStream_t s) {
   const int a = int(h->sym_hi + 1), cnt = int(m_hi - h->sym_hi);
   HIPCHK(fids::launch_kbar(h->hp.kappa, int(fids::natural_len(h->prm)), a, cnt, h->prm.kappa_time_dependent,
-                           at<double>(h->ws, h->lo.kbar), at<double>(h->ws, h->lo.kmax), h->stream));
+                           at<double>(h->ws, h->lo.kbar), at<double>(h->ws, h->lo.kmax), s));
   for (int m0 = a; m0 <= int(m_hi); m0 += h->lo.chunk) {
     const int c = std::min(h->lo.chunk, int(m_hi) - m0 + 1);
-    HIPCHK(fids::launch_symbols(h->hj, h->dj, m0, c, h->stream));
+    HIPCHK(fids::launch_symbols(h->hj, h->dj, m0, c, s));
+    if (h->symflag) HIPCHK(fids::launch_flag(h->symflag, unsigned(m0 + c - 1), s));
   }
   h->sym_hi = m_hi;
   return FIDS_OK;
 }
+
+int ensure_symbols(fids_problem* h, int64_t m_hi) {
+  m_hi = std::min<int64_t>(m_hi, h->sh.M);
+  if (h->sym_hi >= m_hi) return FIDS_OK;
+  return build_symbols(h, m_hi, h->stream);
+}
 int ensure_symbols(fids_problem* h) { return ensure_symbols(h, h->sh.M); }
 
 // One cooperative launch of the level kernel for descriptor `d` and a wait
-// for its status words {status, last completed level}.
+// for its status words {status, last completed level}; `after` (may be null)
+// is an event of other work the stream then waits for as well.
 int launch_wait(fids_problem* h, const Prob& hd, Prob* d, int m_begin, int m_end, int hist_lo, int ckpt_on,
-                int stat[2]) {
+                int stat[2], hipEvent_t after = nullptr) {
   HIPCHK(hipMemsetAsync(h->dabort, 0, sizeof(int), h->stream));
   HIPCHK(fids::launch_levels(hd, d, 1, hd.ng + hd.nh, h->lds, m_begin, m_end, hist_lo, ckpt_on, h->timeout_ticks,
                              h->dabort, h->stream));
+  if (after) HIPCHK(hipStreamWaitEvent(h->stream, after, 0));
   HIPCHK(hipMemcpyAsync(stat, hd.status, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   if (stat[0] == FIDS_EDEVICE) {
@@ -405,11 +424,25 @@ int hist_lo_of(const fids_problem* h) { return h->prm.store_states ? 0 : -1; }
 // entry k for level level+1+k.
 int run_levels(fids_problem* h, int64_t m_end, fids_step_info* infos_host) {
   if (h->level >= h->sh.M || h->poisoned) return FIDS_ESTATE;
-  int st = ensure_symbols(h, m_end);
-  if (st != FIDS_OK) return st;
+  int st = FIDS_OK;
+  hipEvent_t after = nullptr;
+  if (h->sstream && h->sym_hi < m_end && env_int("FIDS_SYM_OVERLAP", 1) != 0) {
+    // the symbols of these levels are built on the symbol stream, a chunk of
+    // levels at a time, on the CUs the solver group leaves free; each level
+    // waits for its own (the first chunk is ready after about 0.2 ms)
+    HIPCHK(hipEventRecord(h->ev_in, h->stream));
+    HIPCHK(hipStreamWaitEvent(h->sstream, h->ev_in, 0));
+    st = build_symbols(h, m_end, h->sstream);
+    if (st != FIDS_OK) return st;
+    HIPCHK(hipEventRecord(h->ev_out, h->sstream));
+    after = h->ev_out;
+  } else {
+    st = ensure_symbols(h, m_end);
+    if (st != FIDS_OK) return st;
+  }
   const int m_begin = int(h->level + 1);
   int stat[2] = {0, 0};
-  st = launch_wait(h, h->hp, h->dp, m_begin, int(m_end), hist_lo_of(h), h->lo.nck > 0, stat);
+  st = launch_wait(h, h->hp, h->dp, m_begin, int(m_end), hist_lo_of(h), h->lo.nck > 0, stat, after);
   if (st != FIDS_OK) return st;
   const int64_t last = stat[1];
   const int64_t first = m_begin;
@@ -461,7 +494,7 @@ void batch_params(fids_params& p, int group = 1) {
 // and synchronises once for all of its members.
 int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, const double* phi_d,
               void* ws_d, size_t ws_bytes, void* hip_stream, int batch_group, fids_problem** out,
-              size_t sym_budget = kSymBudget) {
+              size_t sym_budget = kSymBudget, bool overlap = true) {
   const bool batch = batch_group > 0;
   fids_params pb = *pin;
   if (batch) batch_params(pb, batch_group);
@@ -634,6 +667,19 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
     // snapshots are taken where the solver group streams the history itself
     if (p->checkpoint_every > 0) nh = 0;
     hp.nh = nh;
+    // a problem of its own (not a batch member, not the static entry point)
+    // whose launch leaves at least half of the CUs free builds its symbols
+    // on a second stream while its levels run (the levels wait for them, so
+    // the symbol kernels must find free CUs: helpers that fill the device
+    // rule it out)
+    if (overlap && 2 * (hp.ng + hp.nh) <= cus) {
+      h->symflag = at<unsigned>(ws, lo.symflag);
+      if (hip_bad(hipStreamCreateWithFlags(&h->sstream, hipStreamNonBlocking), __LINE__) ||
+          hip_bad(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming), __LINE__) ||
+          hip_bad(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming), __LINE__))
+        return fail(FIDS_EDEVICE);
+    }
+    hp.symflag = h->symflag;
     if (direct && nh > 0) {
       // active rows of a tile hold the natural value pairs below ceil(n / 2)
       hp.dact = int(((h->sh.n + 1) / 2 + hp.pl.N2 - 1) / hp.pl.N2);
@@ -937,7 +983,7 @@ int fids_solve_static(const fids_params* p, const double* kappa_d, const double*
   fids_problem* h = nullptr;
   // init clears the part of the array the problem uses (the last call's
   // contents are still there)
-  st = init_impl(p, kappa_d, f_d, phi_d, ws, kScratchBytes, hip_stream, 0, &h, kScratchSymBudget);
+  st = init_impl(p, kappa_d, f_d, phi_d, ws, kScratchBytes, hip_stream, 0, &h, kScratchSymBudget, false);
   if (st != FIDS_OK) return st;
   st = run_levels(h, h->sh.M, per_step);
   if (st == FIDS_OK && uT_d) {
@@ -1000,6 +1046,7 @@ int fids_reset(fids_problem* h) {
   HIPCHK(hipMemsetAsync(h->hp.hflag, 0, 4096 * 64, h->stream));
   HIPCHK(hipMemsetAsync(h->hp.status, 0, 4 * sizeof(int), h->stream));
   HIPCHK(hipMemsetAsync(h->hp.bar, 0, fids::kBarBytes, h->stream));
+  if (h->symflag) HIPCHK(hipMemsetAsync(h->symflag, 0, sizeof(unsigned), h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   h->level = 0;
   h->poisoned = false;

@@ -113,6 +113,8 @@ struct Prob {
   double* V;                    // FGMRES: V basis, [restart+1][vlen]
   double* uhist;                // [(M+1)][vlen] when store_states
   double2* T;                   // FFT intermediate, Nc complex
+  const unsigned* symflag;      // highest level whose symbol, kbar and kmax are built (raised by the
+                                //   symbol stream while the levels run), or null: all are built
   float2* Tf;                   // FP32 FFT intermediate, Nc complex
   double* part;                 // [SL_COUNT][ntiles]
   fids_step_info* info;         // [M]

@@ -556,6 +556,7 @@ struct Ctl {
   int hist_lo;     // >= 0: store u^k at uhist[k - hist_lo]; < 0: keep no states
   int ckpt_on;     // forward: write the segment snapshots
   int pending;     // adjoint: the kappa gradient of level m+1 waits in T
+  unsigned sym_seen;  // symbols known to be built up to this level (Prob::symflag)
 };
 
 // FGMRES small state in LDS: hraw (J+1)J, R J*J, and 8 vectors of J+1.
@@ -638,6 +639,38 @@ __device__ __forceinline__ bool wait_ge(const Prob& p, const unsigned* addr, uns
     s_ok = ok;
   }
   __syncthreads();
+  return s_ok != 0;
+}
+
+// Waits until the symbol stream has built level m's symbol, kbar and kmax
+// (Prob::symflag >= m; thread 0 polls with relaxed loads, then one acquire
+// fence as in group_barrier) and remembers the level it saw, so that the
+// levels of a chunk already built pass without a probe.  False on timeout,
+// abort, or the solver group's stop flag.
+__device__ __forceinline__ bool wait_symbols(const Prob& p, int m, Ctl& ctl) {
+  __shared__ unsigned s_seen;
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    unsigned v;
+    const unsigned long long t0 = wall_clock64();
+    while ((v = __hip_atomic_load(p.symflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < unsigned(m)) {
+      __builtin_amdgcn_s_sleep(8);
+      if (__hip_atomic_load(ctl.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+          __hip_atomic_load(&p.status[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
+      if (wall_clock64() - t0 > ctl.timeout) {
+        __hip_atomic_store(ctl.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_seen = v;
+    s_ok = ok;
+  }
+  __syncthreads();
+  ctl.sym_seen = s_seen;
   return s_ok != 0;
 }
 
@@ -2232,6 +2265,7 @@ __device__ __forceinline__ void run_member(const Prob& p, int rank, int m_begin,
   ctl.hist_lo = hist_lo;
   ctl.ckpt_on = ckpt_on;
   ctl.pending = 0;
+  ctl.sym_seen = 0;
   if constexpr (ADJ) {
     for (int m = m_begin; m >= m_end; --m) {
       ctl.pending = m < m_begin;
@@ -2249,7 +2283,9 @@ __device__ __forceinline__ void run_member(const Prob& p, int rank, int m_begin,
     return;
   }
   for (int m = m_begin; m <= m_end; ++m) {
-    const int st = level_solve<VAR>(p, m, rank, ctl, L);
+    int st = FIDS_OK;
+    if (p.symflag && unsigned(m) > ctl.sym_seen && !wait_symbols(p, m, ctl)) st = FIDS_EDEVICE;
+    if (st == FIDS_OK) st = level_solve<VAR>(p, m, rank, ctl, L);
     if (st != FIDS_OK) {
       if (rank == 0 && threadIdx.x == 0) {
         if (st == FIDS_EDEVICE) p.status[0] = FIDS_EDEVICE;
@@ -2462,6 +2498,10 @@ __global__ void __launch_bounds__(kThreads) k_sym_ones(const SymJob* jj, int m0)
   }
 }
 
+__global__ void k_flag(unsigned* flag, unsigned value) {
+  if (threadIdx.x == 0) __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ------------------------------------------------------------- host launchers
 static size_t plan_lds(const Plan& pl) {
   const size_t a = size_t(2) * pl.CT * pl.N1, b = size_t(4) * pl.RU * pl.N2;
@@ -2504,6 +2544,11 @@ hipError_t launch_from_natural(const Prob& h, const Prob* d, const double* src, 
 hipError_t launch_kbar(const double* kappa, int n, int m0, int cnt, int td, double* kbar, double* kmax,
                        hipStream_t s) {
   hipLaunchKernelGGL(k_kbar, dim3(cnt), dim3(kThreads), 0, s, kappa, n, m0, td, kbar, kmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_flag(unsigned* flag, unsigned value, hipStream_t s) {
+  hipLaunchKernelGGL(k_flag, dim3(1), dim3(64), 0, s, flag, value);
   return hipGetLastError();
 }
 

@@ -20,6 +20,8 @@ hipError_t launch_kbar(const double* kappa, int n, int m0, int cnt, int td, doub
 
 // Per-level preconditioner symbols for levels [m0, m0 + cnt).
 hipError_t launch_symbols(const SymJob& job, const SymJob* d, int m0, int cnt, hipStream_t s);
+// *flag = value (agent-scope release), ordered after the stream's earlier work.
+hipError_t launch_flag(unsigned* flag, unsigned value, hipStream_t s);
 
 // LDS bytes of the symbol kernels.
 size_t symbols_lds_bytes(const SymJob& job);

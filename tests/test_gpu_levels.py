@@ -1,5 +1,6 @@
 """GPU tests of stepping through windows of levels (fids_solve_levels) and of
-the per-level acceptance flags.
+the per-level acceptance flags, and of the per-level symbols built on a
+second stream while the levels run.
 
 Advancing a problem in windows of levels runs the same kernels over the same
 levels as one launch over all of them, so the states and level reports must
@@ -111,3 +112,35 @@ def test_stalled_residual_accepted_only_within_rounding_level(solver):
     assert prob.solve_levels_raw(1) == fids.FIDS_ESTATE
     prob.reset()
     prob.close()
+
+
+@pytest.mark.parametrize("kw", FORMS[:2])
+def test_symbols_built_alongside_equal_built_before(kw, monkeypatch):
+    """A solve from level 0 builds the per-level symbols (kbar, kmax and the
+    preconditioner of each level) on a second stream while its levels run,
+    each level waiting for its own; the solution and every level report are
+    bit-identical to a solve whose symbols were all built before the launch
+    (FIDS_SYM_OVERLAP=0), and to runs of levels that build their own levels'
+    symbols alongside."""
+    pb = W.seeded(1.4, 0.4, 4095, 64, kappa_seed=91, f_seed=92)
+    prob = _problem(pb, krylov_tol=1e-10, **kw)
+    try:
+        monkeypatch.setenv("FIDS_SYM_OVERLAP", "0")
+        u0, _, reps0 = prob.solve_all()
+        u0 = u0.cpu().numpy()
+        monkeypatch.setenv("FIDS_SYM_OVERLAP", "1")
+        prob.reset()
+        u1, _, reps1 = prob.solve_all()
+        u1 = u1.cpu().numpy()
+        prob.reset()
+        got = []
+        for c in (1, 9, 30, 24):
+            u2, r2 = prob.solve_levels(c)
+            got += r2
+        u2 = u2.cpu().numpy()
+    finally:
+        prob.close()
+    say(f"  overlap vs before: max diff {np.max(np.abs(u1 - u0)):.3e}, windows {np.max(np.abs(u2 - u0)):.3e}")
+    assert np.array_equal(u1, u0) and np.array_equal(u2, u0)
+    assert [_key(r) for r in reps1] == [_key(r) for r in reps0]
+    assert [_key(r) for r in got] == [_key(r) for r in reps0]
