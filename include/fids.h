@@ -27,6 +27,15 @@
  *     the default stream).  Calls that return device results (u_out_d, uT_d,
  *     gradients) enqueue the writes and synchronise the stream before they
  *     return, because they also report a status computed on the device.
+ *     A problem (not a batch) whose level launch leaves at least half of the
+ *     CUs free also creates one stream of its own (default priority) at
+ *     fids_init_problem: fids_step / fids_solve_levels / fids_solve_all build
+ *     the per-level symbols of the levels they run there, after the work
+ *     already on hip_stream, while the levels run; hip_stream waits for it
+ *     before the call returns.  The symbol stream therefore needs free CUs:
+ *     other work that fills the device while the levels wait for a symbol
+ *     makes the level kernel give up after 4 s (FIDS_EDEVICE).  Such a
+ *     caller builds the symbols first with fids_prepare.
  *   - The library never calls hipMalloc: all device memory it uses lives in
  *     the caller's workspace ws_d of at least fids_workspace_size() bytes
  *     (256-byte aligned).  Host memory for the handle and the set-up tables is
