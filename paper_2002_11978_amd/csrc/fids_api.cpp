@@ -318,9 +318,18 @@ struct fids_batch {
   std::vector<int> groups;       // workgroups of each member's group
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t cap_stream = nullptr;   // capture needs a stream other than the legacy default
+  // members' symbols are built on kBatchSymStreams streams at once (each
+  // member's small symbol kernels leave most of the device idle)
+  static constexpr int kBatchSymStreams = 4;
+  hipStream_t sstreams[kBatchSymStreams] = {};
+  hipEvent_t sev[kBatchSymStreams + 1] = {};
   ~fids_batch() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (hipEvent_t e : sev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipStream_t t : sstreams)
+      if (t) (void)hipStreamDestroy(t);
     for (fids_problem* h : members) delete h;
   }
 };
@@ -898,10 +907,29 @@ hipError_t batch_launch(fids_batch* b, int m0, int m1, hipStream_t s) {
                              b->timeout_ticks, b->dabort, s);
 }
 
+// Members' symbols not yet built, spread over the batch's symbol streams
+// (after the work already on the batch stream, which then waits for them).
 int batch_symbols(fids_batch* b) {
+  constexpr int K = fids_batch::kBatchSymStreams;
+  bool need = false;
+  for (fids_problem* h : b->members) need |= h->sym_hi < h->sh.M;
+  if (!need) return FIDS_OK;
+  if (!b->sstreams[0]) {
+    for (int k = 0; k < K; ++k) HIPCHK(hipStreamCreateWithFlags(&b->sstreams[k], hipStreamNonBlocking));
+    for (hipEvent_t& e : b->sev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  HIPCHK(hipEventRecord(b->sev[K], b->stream));
+  for (int k = 0; k < K; ++k) HIPCHK(hipStreamWaitEvent(b->sstreams[k], b->sev[K], 0));
+  int k = 0;
   for (fids_problem* h : b->members) {
-    const int st = ensure_symbols(h);
+    if (h->sym_hi >= h->sh.M) continue;
+    const int st = build_symbols(h, h->sh.M, b->sstreams[k]);
     if (st != FIDS_OK) return st;
+    k = (k + 1) % K;
+  }
+  for (int j = 0; j < K; ++j) {
+    HIPCHK(hipEventRecord(b->sev[j], b->sstreams[j]));
+    HIPCHK(hipStreamWaitEvent(b->stream, b->sev[j], 0));
   }
   return FIDS_OK;
 }
