@@ -56,7 +56,8 @@
  *   FIDS_TILES       column tiles of the level plan (default: the group size)
  *   FIDS_SKEW        moves factors of two from the column FFT length to the row
  *                    FFT length (default 0)
- *   FIDS_HELPERS     SOE helper workgroups when soe_helpers = -1 (default 0)
+ *   FIDS_HELPERS     SOE helper workgroups when soe_helpers = -1 (default: as
+ *                    many as the solver group has workgroups)
  *   FIDS_BATCH_MODE  "graph": a batch places every member on one workgroup
  *                    and advances by one captured HIP-graph launch per level
  *                    (fids_batch_solve_all from level 0; the graph is captured
@@ -154,8 +155,9 @@ typedef struct fids_params {
     int32_t wg_count;     /* workgroups that cooperate on one problem; 0 = auto    */
     int32_t soe_helpers;  /* workgroups that stream the history one level ahead   */
                           /* of the solve (the SOE recurrence, or the direct sum   */
-                          /* over the stored states): -1 auto (SOE: none; direct:  */
-                          /* every workgroup the solver group leaves free), 0      */
+                          /* over the stored states): -1 auto (SOE: one per        */
+                          /* solver workgroup; direct: every workgroup the solver  */
+                          /* group leaves free), 0                                 */
                           /* none, k > 0 at most k (as many as can be resident     */
                           /* beside the group, at most 1024); 0 when               */
                           /* checkpoint_every > 0                                  */

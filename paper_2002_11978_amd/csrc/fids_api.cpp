@@ -666,12 +666,17 @@ int init_impl(const fids_params* pin, const double* kappa_d, const double* f_d, 
                     "fids_api.cpp:%d: %d workgroups cannot be co-resident (%d fit)", __LINE__, hp.ng, resident);
       return fail(FIDS_EDEVICE);
     }
-    // auto = none: on MI355X at n = 65535 the helpers' stream slowed the
-    // latency-bound solve more than it saved (976 -> 897 levels/s with 128)
-    // The direct history's sum over every earlier state, on the other hand,
-    // is a stream of m n values per level: auto = every free workgroup.
+    // SOE history, auto = one helper per solver workgroup: the helpers take
+    // the history stream (2 nexp n values per level) out of the solver's
+    // right-hand-side phase.  Measured on MI355X, PCG form: n = 65535 with
+    // 64 + 64 workgroups 738 -> 720 ms per 2048 levels (32: 731, 96: 728,
+    // 128: 736); n = 16383, 16 + 16: 345 -> 329 ms per 1024 levels; n = 4095,
+    // 4 + 4: 174 -> 166 ms per 512 levels.  The direct history's sum over
+    // every earlier state is a stream of m n values per level: auto = every
+    // free workgroup.
     const bool direct = p->history == FIDS_HISTORY_DIRECT;
-    int nh = p->soe_helpers >= 0 ? p->soe_helpers : (direct ? fids::kMaxHelpers : env_int("FIDS_HELPERS", 0));
+    int nh = p->soe_helpers >= 0 ? p->soe_helpers
+                                 : (direct ? fids::kMaxHelpers : env_int("FIDS_HELPERS", hp.ng));
     nh = std::max(0, std::min({nh, resident - hp.ng, fids::kMaxHelpers}));
     // snapshots are taken where the solver group streams the history itself
     if (p->checkpoint_every > 0) nh = 0;

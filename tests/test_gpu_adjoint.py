@@ -102,11 +102,13 @@ def test_adjoint_matches_oracle(n, M, td, kw):
 @pytest.mark.parametrize("C", [1, 3, 5, 16, 40])
 def test_checkpointed_equals_stored_states(C, kw):
     """Segments recomputed from snapshots give the stored-states gradients
-    exactly (the recomputation is the same deterministic computation)."""
+    exactly (the recomputation is the same deterministic computation; both
+    forward runs stream the history in the solver group, as snapshots
+    require, so that the history sums share their rounding order)."""
     pb = W.seeded(1.3, 0.6, 2047, 33, kappa_seed=21, f_seed=22, time_dependent=True)
     ustar = _target(pb, 23)
-    full, _ = _gpu_grads(pb, ustar, store_states=1, wg_count=4, **kw)
-    ck, _ = _gpu_grads(pb, ustar, store_states=0, checkpoint_every=C, wg_count=4, **kw)
+    full, _ = _gpu_grads(pb, ustar, store_states=1, wg_count=4, soe_helpers=0, **kw)
+    ck, _ = _gpu_grads(pb, ustar, store_states=0, checkpoint_every=C, wg_count=4, soe_helpers=0, **kw)
     for a, b in zip(full, ck):
         assert np.array_equal(a, b)
 
@@ -114,8 +116,10 @@ def test_checkpointed_equals_stored_states(C, kw):
 def test_checkpoint_snapshots_do_not_change_the_forward():
     pb = W.seeded(1.5, 0.4, 1023, 20, kappa_seed=31, f_seed=32)
     outs = []
+    # without helper workgroups in all three (snapshots turn them off; they
+    # change the history sums' rounding order)
     for kw in (dict(), dict(checkpoint_every=3), dict(store_states=1)):
-        p = _params(pb, solver=1, x0_mode=3, **kw)
+        p = _params(pb, solver=1, x0_mode=3, soe_helpers=0, **kw)
         prob = fids.Problem(p, to_dev(pb.kappa), to_dev(pb.f), to_dev(pb.phi))
         uT, _, _ = prob.solve_all()
         outs.append(uT.cpu().numpy())
@@ -251,8 +255,9 @@ def test_autograd_function_matches_adjoint():
     from paper_2002_11978_amd import autograd as AG
     pb = W.seeded(1.5, 0.4, 511, 24, kappa_seed=51, f_seed=52, time_dependent=True)
     ustar = _target(pb, 53)
-    (gk, gf, gphi, uT), _ = _gpu_grads(pb, ustar, store_states=1, solver=1, x0_mode=1)
-    p = _params(pb, solver=1, x0_mode=1)
+    # the wrapper checkpoints (no helper workgroups): so does the reference
+    (gk, gf, gphi, uT), _ = _gpu_grads(pb, ustar, store_states=1, solver=1, x0_mode=1, soe_helpers=0)
+    p = _params(pb, solver=1, x0_mode=1, soe_helpers=0)
     kap = to_dev(pb.kappa).requires_grad_(True)
     f = to_dev(pb.f).requires_grad_(True)
     phi = to_dev(pb.phi).requires_grad_(True)

@@ -39,6 +39,9 @@ def _batch(pbs, **kw):
 
 
 def _solo(pb, wg=1, **kw):
+    # batch members stream their history themselves (no helper workgroups):
+    # so does the solo run it is compared with bit for bit
+    kw.setdefault("soe_helpers", 0)
     prob = fids.Problem(_params(pb, wg_count=wg, **kw), to_dev(pb.kappa), to_dev(pb.f), to_dev(pb.phi))
     uT, _, reps = prob.solve_all()
     out = uT.cpu().numpy()
