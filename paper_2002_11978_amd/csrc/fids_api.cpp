@@ -412,10 +412,14 @@ int ensure_symbols(fids_problem* h) { return ensure_symbols(h, h->sh.M); }
 // is an event of other work the stream then waits for as well.
 int launch_wait(fids_problem* h, const Prob& hd, Prob* d, int m_begin, int m_end, int hist_lo, int ckpt_on,
                 int stat[2], hipEvent_t after = nullptr) {
-  HIPCHK(hipMemsetAsync(h->dabort, 0, sizeof(int), h->stream));
-  HIPCHK(fids::launch_levels(hd, d, 1, hd.ng + hd.nh, h->lds, m_begin, m_end, hist_lo, ckpt_on, h->timeout_ticks,
-                             h->dabort, h->stream));
+  const hipError_t ez = hipMemsetAsync(h->dabort, 0, sizeof(int), h->stream);
+  const hipError_t el = ez != hipSuccess ? ez
+                        : fids::launch_levels(hd, d, 1, hd.ng + hd.nh, h->lds, m_begin, m_end, hist_lo, ckpt_on,
+                                              h->timeout_ticks, h->dabort, h->stream);
+  // the stream waits for the other work even when the launch failed, so that
+  // nothing enqueued on it later overlaps that work
   if (after) HIPCHK(hipStreamWaitEvent(h->stream, after, 0));
+  if (hip_bad(el, __LINE__)) return FIDS_EDEVICE;
   HIPCHK(hipMemcpyAsync(stat, hd.status, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   if (stat[0] == FIDS_EDEVICE) {
@@ -442,8 +446,11 @@ int run_levels(fids_problem* h, int64_t m_end, fids_step_info* infos_host) {
     HIPCHK(hipEventRecord(h->ev_in, h->stream));
     HIPCHK(hipStreamWaitEvent(h->sstream, h->ev_in, 0));
     st = build_symbols(h, m_end, h->sstream);
-    if (st != FIDS_OK) return st;
     HIPCHK(hipEventRecord(h->ev_out, h->sstream));
+    if (st != FIDS_OK) {
+      HIPCHK(hipStreamWaitEvent(h->stream, h->ev_out, 0));
+      return st;
+    }
     after = h->ev_out;
   } else {
     st = ensure_symbols(h, m_end);
@@ -925,18 +932,19 @@ int batch_symbols(fids_batch* b) {
   }
   HIPCHK(hipEventRecord(b->sev[K], b->stream));
   for (int k = 0; k < K; ++k) HIPCHK(hipStreamWaitEvent(b->sstreams[k], b->sev[K], 0));
-  int k = 0;
+  int k = 0, st = FIDS_OK;
   for (fids_problem* h : b->members) {
     if (h->sym_hi >= h->sh.M) continue;
-    const int st = build_symbols(h, h->sh.M, b->sstreams[k]);
-    if (st != FIDS_OK) return st;
+    st = build_symbols(h, h->sh.M, b->sstreams[k]);
+    if (st != FIDS_OK) break;
     k = (k + 1) % K;
   }
+  // the batch stream waits for whatever was enqueued, also after a failure
   for (int j = 0; j < K; ++j) {
     HIPCHK(hipEventRecord(b->sev[j], b->sstreams[j]));
     HIPCHK(hipStreamWaitEvent(b->stream, b->sev[j], 0));
   }
-  return FIDS_OK;
+  return st;
 }
 
 // Waits for a batch launch over levels [m0, m1] and folds the members' status
